@@ -1,0 +1,274 @@
+"""Pins for the CPU oracle: printed examples, closed forms, invariants, brute force.
+
+None of these tests uses the HIP library.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from conftest import load_golden
+from oracle import brute, core
+from paper_2504_02271_amd import synth
+
+
+def _graph(edges, n=None):
+    g = synth.from_lists(edges, n)
+    return core.OracleGraph(g.offsets, g.members, g.num_vertices)
+
+
+# ---------------------------------------------------------------- patterns
+
+def test_twenty_closed_classes_split_like_the_paper():
+    """Enumerating all 2^7 region-emptiness masks under relabelling gives
+    exactly the 20 patterns of Section 2, split 1/4/3/12 over CCC/TCC/TTC/TTT
+    and 8/4 over DenseTTT/SparseTTT (Section 3.2)."""
+    classes = brute.closed_classes()
+    assert len(classes) == 20
+    assert set(classes) == set(brute.CANON_TO_PATTERN)
+    by_class = {}
+    for p, regions in brute.WITNESS.items():
+        ei, ej, ek = _witness_sets(regions)
+        inc = sum(1 for x, y in ((ei, ej), (ej, ek), (ei, ek)) if x <= y or y <= x)
+        by_class.setdefault(inc, []).append(p)
+        if inc == 0:
+            assert (p <= 16) == bool(ei & ej & ek)       # Dense iff a common vertex
+    assert sorted(by_class[3]) == [1]
+    assert sorted(by_class[2]) == [2, 3, 4, 5]
+    assert sorted(by_class[1]) == [6, 7, 8]
+    assert sorted(by_class[0]) == list(range(9, 21))
+
+
+def _witness_sets(regions):
+    """Three hyperedges with one fresh vertex per non-empty region."""
+    member = {"a": "i", "b": "j", "c": "k", "d": "ij", "e": "jk", "f": "ik", "g": "ijk"}
+    e = {"i": set(), "j": set(), "k": set()}
+    for v, ch in enumerate(regions):
+        for x in member[ch]:
+            e[x].add(v)
+    return e["i"], e["j"], e["k"]
+
+
+@pytest.mark.parametrize("p", range(1, 21))
+def test_witness_graph_gives_one_triangle_of_its_pattern(p):
+    ei, ej, ek = _witness_sets(brute.WITNESS[p])
+    for perm in itertools.permutations([ei, ej, ek]):       # any hyperedge order
+        o = _graph([sorted(x) for x in perm])
+        r = o.count(nthreads=1)
+        want = np.zeros(21, np.int64)
+        want[0] = want[p] = 1
+        assert (r.H == want).all(), (p, r.H)
+        assert (r.t == 1).all()
+
+
+def test_algorithm5_rules_on_direct_cases():
+    """Patterns 1-8 straight from the arithmetic of Algorithm 5."""
+    # CCC: chain {1} < {1,2} < {1,2,3}
+    assert core.classify(1, 2, 3, 1, 1, 2, 1) == 1
+    # TCC, k inside both i and j: omega_ij > |e_k| -> 3, else 2
+    # i={1,2,3}, j={1,2,4}, k={1}: omega_ij=2 > 1 -> 3
+    assert core.classify(3, 3, 1, 2, 1, 1, 1) == 3
+    # i={1,2}, j={1,3}, k={1}: omega_ij = 1 = |e_k| -> 2
+    assert core.classify(2, 2, 1, 1, 1, 1, 1) == 2
+    # TCC, k contains both: omega_ki + omega_kj - omega_ij = |e_k| -> 4 else 5
+    # i={1,2}, j={2,3}, k={1,2,3} -> 4 ; k={1,2,3,4} -> 5
+    assert core.classify(2, 2, 3, 1, 2, 2, 1) == 4
+    assert core.classify(2, 2, 4, 1, 2, 2, 1) == 5
+    # TTC with L={1,2,3}, S={1,2}, X: omega_LX = omega_SX -> 6
+    # X={1,9}: omega_LX=1, omega_SX=1
+    assert core.classify(3, 2, 2, 2, 1, 1, 1) == 6
+    # X={1,3,9}: omega_LX=2, omega_SX=1, omega_LS+omega_LX-omega_SX = 3 = |L| -> 7
+    assert core.classify(3, 2, 3, 2, 2, 1, 1) == 7
+    # L={1,2,3,4}, S={1,2}, X={1,3,9}: 2+2-1 = 3 != 4 -> 8
+    assert core.classify(4, 2, 3, 2, 2, 1, 1) == 8
+
+
+# ---------------------------------------------------------------- printed examples
+
+def test_fig6_coauthorship_listed_triangles():
+    edges, tris, _ = load_golden("fig6_coauthorship.txt")
+    E = [set(e) for e in edges]
+    for (x, y, z), p in tris:
+        si, sj, sk = len(E[x]), len(E[y]), len(E[z])
+        got = core.classify(si, sj, sk, len(E[x] & E[y]), len(E[x] & E[z]), len(E[y] & E[z]),
+                            len(E[x] & E[y] & E[z]))
+        assert got == p
+    # the listed triangles are closed by the oracle's step 2 with the same pattern
+    o = _graph(edges)
+    wi, wj, _ = o.wedges()
+    for (x, y, z), p in tris:
+        a, b, c = sorted((x, y, z))
+        cl = o.wedge_closure(np.array([a]), np.array([b]))
+        assert cl[0, p] >= 1
+    # the figure shows a selection; the full count agrees with brute force
+    H, _ = brute.count(edges)
+    assert (o.count(nthreads=1).H == H).all()
+    assert H[0] == 7 and H[10] == 5 and H[12] == 2
+
+
+def test_fig7_email_every_triangle_is_pattern_5():
+    edges, tris, complete = load_golden("fig7_email.txt")
+    assert complete
+    o = _graph(edges)
+    r = o.count(nthreads=1)
+    want = np.zeros(21, np.int64)
+    want[0] = want[5] = len(tris)
+    assert (r.H == want).all()
+    # e_1 is in all three, e_4 in two
+    assert r.t.tolist() == [3, 1, 1, 2, 1, 1]
+
+
+# ---------------------------------------------------------------- closed forms
+
+def test_nested_chain_is_pattern_1():
+    k = 9
+    edges = [list(range(r + 1)) for r in range(k)]
+    r = _graph(edges).count(nthreads=1)
+    assert r.H[1] == math.comb(k, 3) and r.H[0] == math.comb(k, 3)
+
+
+def test_sunflower_is_common_vertex_pattern():
+    k = 12
+    edges = [[0, 1 + 2 * r, 2 + 2 * r] for r in range(k)]
+    r = _graph(edges).count(nthreads=1)
+    assert r.H[9] == math.comb(k, 3) and r.H[0] == math.comb(k, 3)
+    assert (r.t == math.comb(k - 1, 2)).all()
+
+
+def test_two_uniform_hypergraph_is_a_simple_graph():
+    """Edges of a simple graph: three pairwise-meeting edges are a star
+    (pattern 9, count sum_v C(deg_v, 3)) or a graph triangle (pattern 17)."""
+    nx = pytest.importorskip("networkx")
+    G = nx.gnm_random_graph(60, 300, seed=7)
+    edges = [sorted(e) for e in G.edges()]
+    r = _graph(edges, 60).count(nthreads=2)
+    stars = sum(math.comb(d, 3) for _, d in G.degree())
+    tri = sum(nx.triangles(G).values()) // 3
+    assert r.H[9] == stars
+    assert r.H[17] == tri
+    assert r.H[0] == stars + tri
+
+
+def test_total_equals_intersection_graph_triangles_and_W():
+    sp = pytest.importorskip("scipy.sparse")
+    g = synth.generate(synth.config("tiny"))
+    o = core.OracleGraph(g.offsets, g.members, g.num_vertices)
+    off, mem, _ = o.csr()
+    m = off.shape[0] - 1
+    rows = np.repeat(np.arange(m), np.diff(off))
+    B = sp.csr_matrix((np.ones(rows.shape[0]), (rows, mem)), shape=(m, g.num_vertices))
+    A = (B @ B.T).tocsr()
+    A.setdiag(0)
+    A.eliminate_zeros()
+    A.data[:] = 1.0
+    tri = int(round((A @ A).multiply(A).sum() / 6))
+    deg = np.asarray(A.sum(axis=1)).ravel().astype(np.int64)
+    r = o.count()
+    s = o.summary()
+    assert r.H[0] == tri
+    assert r.H[1:].sum() == r.H[0]
+    assert s[0] == A.nnz // 2
+    assert s[3] == int((deg * (deg - 1) // 2).sum())
+    assert (o.degrees() == deg).all()
+    assert r.t.sum() == 3 * r.H[0]
+
+
+# ---------------------------------------------------------------- brute force
+
+@pytest.mark.parametrize("seed", range(12))
+def test_oracle_matches_brute_force(seed):
+    g = synth.random_small(seed, 50 + 5 * seed, 5 + 3 * seed, 1, 6)
+    edges = [g.edge(x).tolist() for x in range(g.num_edges)]
+    H, t = brute.count(edges)
+    o = core.OracleGraph(g.offsets, g.members, g.num_vertices)
+    r = o.count(nthreads=3, per_wedge=True)
+    assert (r.H == H).all()
+    assert (r.t == t).all()
+    # hyperwedges with omega and type
+    wi, wj, wo = o.wedges()
+    bw = brute.hyperwedges(edges)
+    assert [(int(a), int(b), int(c)) for a, b, c in zip(wi, wj, wo)] == [w[:3] for w in bw]
+    s = o.summary()
+    assert s[2] == sum(1 for w in bw if w[3]) and s[1] == sum(1 for w in bw if not w[3])
+    # per-wedge forward closure
+    E = brute.normalise(edges)
+    for q, (i, j) in enumerate(zip(wi.tolist(), wj.tolist())):
+        want = sum(1 for k in range(j + 1, len(E)) if E[i] & E[k] and E[j] & E[k])
+        assert r.cw[q] == want
+    assert r.cw.sum() == r.H[0]
+    # per-pattern split of the wedge closure adds up to H
+    cl = o.wedge_closure(wi, wj)
+    assert (cl.sum(axis=0)[1:] == H[1:]).all()
+
+
+def test_all_patterns_occur_in_the_brute_force_families():
+    tot = np.zeros(21, np.int64)
+    for seed in range(12):
+        g = synth.random_small(seed, 50 + 5 * seed, 5 + 3 * seed, 1, 6)
+        tot += core.OracleGraph(g.offsets, g.members, g.num_vertices).count(nthreads=2).H
+    assert (tot[1:] > 0).all(), tot
+
+
+# ---------------------------------------------------------------- invariants
+
+def test_relabelling_and_disjoint_union():
+    rng = np.random.default_rng(3)
+    g = synth.random_small(5, 80, 14, 1, 6)
+    edges = [g.edge(x).tolist() for x in range(g.num_edges)]
+    base = _graph(edges, 14).count(nthreads=2)
+    # relabel vertices and reorder hyperedges (duplicates may exist: keep the
+    # first-occurrence rule consistent by removing them first)
+    uniq = [sorted(e) for e in brute.normalise(edges)]
+    base_u = _graph(uniq, 14).count(nthreads=2)
+    assert (base_u.H == base.H).all()
+    vperm = rng.permutation(14)
+    eperm = rng.permutation(len(uniq))
+    shuffled = [[int(vperm[v]) for v in rng.permutation(uniq[x])] for x in eperm]
+    r = _graph(shuffled, 14).count(nthreads=2)
+    assert (r.H == base_u.H).all()
+    assert (r.t == base_u.t[eperm]).all()
+    # disjoint union adds the counts
+    other = [[v + 14 for v in e] for e in uniq]
+    ru = _graph(uniq + other, 28).count(nthreads=2)
+    assert (ru.H == 2 * base_u.H).all()
+
+
+def test_clustering_coefficients_in_unit_interval():
+    g = synth.generate(synth.config("tiny"))
+    o = core.OracleGraph(g.offsets, g.members, g.num_vertices)
+    r = o.count()
+    deg = o.degrees()
+    pairs = deg * (deg - 1) // 2
+    cc = np.where(pairs > 0, r.t / np.maximum(pairs, 1), 0.0)
+    assert (cc >= 0).all() and (cc <= 1).all()
+    W = o.summary()[3]
+    assert 0 <= 3 * r.H[0] / W <= 1
+
+
+# ---------------------------------------------------------------- input contract
+
+def test_duplicates_and_errors():
+    edges = [[1, 2], [2, 3], [2, 1], [3, 2, 2]]
+    g = synth.from_lists(edges, 4)
+    o = core.OracleGraph(g.offsets, g.members, 4, dedupe=True)
+    off, mem, orig = o.csr()
+    assert o.removed == 2 and orig.tolist() == [0, 1]
+    assert mem.tolist() == [1, 2, 2, 3]
+    with pytest.raises(core.OracleError) as ei:
+        core.OracleGraph(g.offsets, g.members, 4, dedupe=False)
+    assert ei.value.code == -4
+    bad = synth.from_lists([[1, 2], []], 4)
+    with pytest.raises(core.OracleError) as ei:
+        core.OracleGraph(bad.offsets, bad.members, 4)
+    assert ei.value.code == -3
+    with pytest.raises(core.OracleError) as ei:
+        core.OracleGraph(g.offsets, g.members, 3)
+    assert ei.value.code == -2
+
+
+def test_empty_hypergraph():
+    o = core.OracleGraph(np.zeros(1, np.int64), np.zeros(0, np.int32), 0)
+    r = o.count(nthreads=1)
+    assert o.m == 0 and (r.H == 0).all()
+    assert o.summary().tolist() == [0, 0, 0, 0, 0, 0]
