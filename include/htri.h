@@ -1,0 +1,236 @@
+/*
+ * htri -- hyper-triangle counting on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the HIP library libhtri.so.  Plain pointers and sizes only.
+ *
+ * The library implements the two-step method of Yin et al., "Efficient
+ * Computation of Hyper-triangles on Hypergraphs" (PVLDB 18(3), 2024):
+ *
+ *   htri_graph_load      normalise a hypergraph (Def. 2.1: a hyperedge is a
+ *                        non-empty vertex set; Section 2: no two hyperedges
+ *                        hold the same set) and build the vertex->hyperedge
+ *                        lists E_v (Algorithm 2, first step).
+ *   htri_build_wedges    step 1 (Algorithm 2): every hyperwedge (pair of
+ *                        hyperedges sharing a vertex, Def. 2.2) with its
+ *                        common-vertex count omega and common-vertex set
+ *                        Omega; its type (Def. 2.3) follows from omega.
+ *   htri_count_patterns  step 2 (Algorithms 3 and 5, combined as the paper's
+ *                        Exact-adv): close every hyperwedge with each third
+ *                        hyperedge adjacent to both, classify the triple into
+ *                        one of the 20 patterns by which of its seven regions
+ *                        (Section 2, after Def. 2.4) are empty, and reduce
+ *                        per-pattern counts (H of Table 1) and per-hyperedge
+ *                        counts (input of the clustering coefficient,
+ *                        Def. 5.1).
+ *   htri_estimate        hyperwedge sampling (Algorithm 6 with sigma = 1,
+ *                        unbiased by Lemma 4.1), with a uniform proposal or a
+ *                        learned importance proposal.
+ *   htri_model_*         the proposal network (16 -> 64 -> 64 -> 1, ReLU) and
+ *                        its training kernels.
+ *   htri_batch_*         many independent hypergraphs counted in one launch.
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns an htri_status; no C++ exception crosses the ABI.
+ *    On error the outputs are left unchanged and the handle stays usable;
+ *    htri_last_error() describes the failure.
+ *  - Device work runs on the stream given at load time (NULL = the default
+ *    stream).  Functions that fill host arrays synchronise that stream before
+ *    returning.
+ *  - Internal order: hyperedges are processed in the order "prec" defined by
+ *    (delta_x, x) ascending, delta_x = sum over v in e_x of (|E_v| - 1), x the
+ *    normalised id (HTRI_ORDER_INPUT selects plain id order instead).  A
+ *    hyperwedge is stored once, oriented from the earlier to the later
+ *    hyperedge in this order; each hyper-triangle is found exactly once, at
+ *    its two earliest hyperedges (the role of the hyperwedge order O of
+ *    Section 2).  Pattern and per-hyperedge counts do not depend on the order;
+ *    per-wedge closure counts do, and are reported together with the
+ *    orientation (htri_get_wedges).
+ *  - Normalised ids: surviving hyperedges renumbered 0..m-1 in input order
+ *    (later duplicates dropped).  Per-hyperedge outputs use normalised ids.
+ *  - Pattern numbering: 1 (CCC), 2-5 (TCC), 6-8 (TTC), 9-16 (DenseTTT),
+ *    17-20 (SparseTTT).  Counts arrays have 21 entries: [0] = total,
+ *    [p] = pattern p.
+ *  - Not re-entrant on one handle; distinct handles may be used from
+ *    distinct threads.
+ */
+#ifndef HTRI_H
+#define HTRI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HTRI_OK = 0,
+    HTRI_E_INVALID = -1,          /* bad argument or malformed CSR            */
+    HTRI_E_RANGE = -2,            /* vertex id outside [0, num_vertices)      */
+    HTRI_E_EMPTY_EDGE = -3,       /* a hyperedge with no vertex (Def. 2.1)    */
+    HTRI_E_DUPLICATE_EDGE = -4,   /* two equal hyperedges, dedupe not asked   */
+    HTRI_E_OOM = -5,              /* device allocation failed                 */
+    HTRI_E_DEVICE = -6,           /* a HIP runtime error                      */
+    HTRI_E_OVERFLOW = -7,         /* counts could exceed int64                */
+    HTRI_E_STATE = -8,            /* call order (e.g. count before wedges)    */
+    HTRI_E_UNSUPPORTED = -9       /* size beyond what this build handles      */
+} htri_status;
+
+typedef struct htri_graph htri_graph;
+
+/* Optional device allocator (e.g. a framework's caching allocator).
+ * alloc returns a device pointer of at least `bytes` bytes usable on
+ * `stream`, or NULL; free releases it.  NULL allocator = hipMalloc/hipFree. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *ctx);
+    void (*free)(void *ptr, void *stream, void *ctx);
+    void *ctx;
+} htri_allocator;
+
+#define HTRI_DEDUPE_EDGES 1u      /* drop later duplicate hyperedges          */
+#define HTRI_INPUT_ON_DEVICE 2u   /* offsets/members are device pointers      */
+#define HTRI_OUTPUT_ON_DEVICE 4u  /* per_edge / per_wedge are device pointers */
+#define HTRI_ORDER_INPUT 8u       /* orient by normalised id, not by delta    */
+
+/* Load and normalise a hypergraph (Def. 2.1 and the distinct-hyperedge
+ * assumption of Section 2), build E_v (Algorithm 2).
+ *   edge_offsets  int64[num_edges+1], edge_offsets[0] == 0, non-decreasing;
+ *                 hyperedge x holds members[edge_offsets[x] .. edge_offsets[x+1]).
+ *   members       int32[edge_offsets[num_edges]], ids in [0, num_vertices);
+ *                 any order; a repeated id inside one hyperedge counts once.
+ *   flags         HTRI_DEDUPE_EDGES | HTRI_INPUT_ON_DEVICE | HTRI_ORDER_INPUT.
+ *   alloc         NULL or an allocator used for every device buffer.
+ *   stream        hipStream_t (NULL = default stream).
+ *   out           receives the handle; caller frees it with htri_graph_free.
+ * The input arrays are only read during the call and remain the caller's.
+ * Errors: HTRI_E_INVALID, HTRI_E_RANGE, HTRI_E_EMPTY_EDGE,
+ * HTRI_E_DUPLICATE_EDGE, HTRI_E_OOM, HTRI_E_DEVICE, HTRI_E_UNSUPPORTED.
+ * On error *out is NULL and htri_last_error(NULL) describes the failure. */
+htri_status htri_graph_load(const int64_t *edge_offsets, int64_t num_edges, const int32_t *members,
+                            int32_t num_vertices, uint32_t flags, const htri_allocator *alloc,
+                            void *stream, htri_graph **out);
+
+/* Normalised sizes: out[0] = m (hyperedges kept), out[1] = duplicates removed,
+ * out[2] = nnz after removing repeated vertex ids, out[3] = num_vertices. */
+htri_status htri_graph_info(const htri_graph *g, int64_t out[4]);
+
+/* Normalised id -> input index, int64[m] host array. */
+htri_status htri_graph_edge_map(const htri_graph *g, int64_t *new_to_input);
+
+/* Normalised CSR (members sorted ascending within each hyperedge), host
+ * arrays int64[m+1] and int32[nnz]. */
+htri_status htri_graph_csr(const htri_graph *g, int64_t *offsets, int32_t *members);
+
+/* Step 1 (Algorithm 2): build every hyperwedge with omega and Omega.
+ *   summary (may be NULL) int64[6]: |wedges|, |intersection-type|,
+ *   |inclusion-type|, W = sum_x C(deg_x, 2) with deg_x = |N_{e_x}| (the
+ *   connected triples), max omega, m.
+ * Errors: HTRI_E_OOM, HTRI_E_DEVICE, HTRI_E_OVERFLOW (W beyond int64),
+ * HTRI_E_UNSUPPORTED (m or omega too large for the packed adjacency). */
+htri_status htri_build_wedges(htri_graph *g, int64_t summary[6]);
+
+/* Release the step-1 state (hyperwedges, masks) so that htri_build_wedges
+ * runs again; the loaded hypergraph stays.  Used to time step 1 repeatedly
+ * and to free device memory between counts. */
+htri_status htri_clear_wedges(htri_graph *g);
+
+/* Wedges in the library's internal order, oriented src -> dst (src earlier
+ * in prec), normalised ids, host arrays of |wedges| entries; omega may be
+ * NULL.  This is the order of per_wedge in htri_count_patterns. */
+htri_status htri_get_wedges(const htri_graph *g, int32_t *src, int32_t *dst, int32_t *omega);
+
+/* Step 2 (Algorithms 3 and 5 as Exact-adv): exact count of every pattern.
+ *   per_edge_pattern_mask  bit p (1..20) set: triangles of pattern p count
+ *                          in per_edge.  0 is taken as "all patterns".
+ *   counts      int64[21] host array: [0] total, [p] pattern p.
+ *   per_edge    NULL or int64[m]: per normalised hyperedge, the number of
+ *               masked triangles containing it (host or device array, see
+ *               HTRI_OUTPUT_ON_DEVICE in out_flags).
+ *   per_wedge   NULL or int32[|wedges|]: per hyperwedge (htri_get_wedges
+ *               order), the number of third hyperedges that close it and
+ *               come after dst in prec (all patterns).
+ *   out_flags   0 or HTRI_OUTPUT_ON_DEVICE.
+ * Errors: HTRI_E_STATE (no wedges yet), HTRI_E_OOM, HTRI_E_DEVICE. */
+htri_status htri_count_patterns(htri_graph *g, uint32_t per_edge_pattern_mask, int64_t counts[21],
+                                int64_t *per_edge, int32_t *per_wedge, uint32_t out_flags);
+
+/* Device time of the stages of the last htri_build_wedges +
+ * htri_count_patterns, milliseconds: [0] wedge build, [1] schedule,
+ * [2] closure kernel, [3] reduce.  Measured with HIP events on the
+ * handle's stream. */
+htri_status htri_last_timings(const htri_graph *g, double ms[4]);
+
+/* Work census of the last htri_count_patterns: out[0] = S, the closure
+ * stream sum over hyperwedges (r, j) of |N+(j)| (the entries the method must
+ * examine); out[1] = entries the kernel actually probed (partner lists are
+ * cut to each chunk's rank range); out[2] = work items; out[3] = 32-bit
+ * Omega mask words stored; out[4] = closure blocks launched. */
+htri_status htri_closure_stats(const htri_graph *g, int64_t out[5]);
+
+/* ---------------------------------------------------------------- sampling */
+
+typedef struct htri_model htri_model;
+
+typedef struct {
+    double budget_fraction;   /* samples = budget_fraction * |wedges| ...      */
+    int64_t num_samples;      /* ... unless num_samples > 0                    */
+    uint64_t seed;            /* Philox-4x32-10 key                            */
+    int32_t proposal;         /* 0 = uniform, 1 = learned                      */
+    int32_t reserved;
+    const htri_model *model;  /* required for proposal 1                       */
+    double defensive_mix;     /* lambda: q = (1-lambda) q_model + lambda/|pool| */
+    double pool_factor;       /* learned: candidate pool = pool_factor*samples  */
+                              /* (<= 0: the pool is every wedge)                */
+} htri_sample_params;
+
+/* Hyperwedge-sampling estimate (Algorithm 6, sigma = 1; unbiased by Lemma
+ * 4.1, and for any positive proposal by importance weighting).
+ *   est       double[21] host array: estimated H, [0] = total.
+ *   stderr_   NULL or double[21]: standard error of each estimate.
+ *   time_ms   NULL or double: device time of the estimate.
+ * Errors: HTRI_E_STATE, HTRI_E_INVALID, HTRI_E_OOM, HTRI_E_DEVICE. */
+htri_status htri_estimate(htri_graph *g, const htri_sample_params *p, double est[21],
+                          double stderr_[21], double *time_ms);
+
+/* Close an explicit list of wedges (indices into the htri_get_wedges order)
+ * and return per-pattern closure counts, int64[n*21] host array (row w:
+ * [0] total, [p] pattern p).  The sampling kernels' closure step. */
+htri_status htri_close_wedges(htri_graph *g, const int64_t *wedge_idx, int64_t n, int64_t *out);
+
+/* Per-wedge proposal features (16 float32 per wedge, htri_get_wedges order)
+ * into a device array float[|wedges|*16]. */
+htri_status htri_wedge_features(htri_graph *g, float *dev_features);
+
+/* Proposal network 16 -> 64 -> 64 -> 1 with ReLU, float32 weights.
+ * Parameter layout (htri_model_params): W1[64][16], b1[64], W2[64][64],
+ * b2[64], w3[64], b3 -- 5313 floats. */
+#define HTRI_MODEL_NUM_PARAMS 5313
+htri_status htri_model_create(uint64_t seed, void *stream, htri_model **out);
+void htri_model_free(htri_model *m);
+htri_status htri_model_get_params(const htri_model *m, float *host_params);
+htri_status htri_model_set_params(htri_model *m, const float *host_params);
+/* Forward over n feature rows (device arrays): out[n] = network output. */
+htri_status htri_model_forward(const htri_model *m, const float *dev_x, int64_t n, float *dev_out);
+/* Mean-squared-error loss 0.5*mean((f(x)-y)^2) and its gradient with
+ * respect to every parameter (device arrays x[n*16], y[n]; host grad
+ * float[HTRI_MODEL_NUM_PARAMS]); loss written to *loss. */
+htri_status htri_model_loss_grad(const htri_model *m, const float *dev_x, const float *dev_y,
+                                 int64_t n, double *loss, float *host_grad);
+/* Adam training on device rows x[n*16], targets y[n]: `steps` minibatch
+ * steps of `batch` rows drawn with a Philox stream from `seed`. *final_loss
+ * receives the last minibatch loss. */
+htri_status htri_model_train(htri_model *m, const float *dev_x, const float *dev_y, int64_t n,
+                             int32_t steps, int32_t batch, float lr, uint64_t seed,
+                             double *final_loss);
+
+/* ---------------------------------------------------------------- misc */
+
+const char *htri_status_string(htri_status s);
+/* Message of the last failure on g (g NULL: the last failed load). */
+const char *htri_last_error(const htri_graph *g);
+void htri_graph_free(htri_graph *g); /* NULL-safe */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HTRI_H */

@@ -65,6 +65,14 @@ def _load():
     lib.orc_count.restype = ctypes.c_int
     lib.orc_wedge_closure.argtypes = [P, P, P, i64, P]
     lib.orc_wedge_closure.restype = ctypes.c_int
+    lib.orc_build_vertex_lists.argtypes = [P]
+    lib.orc_build_vertex_lists.restype = ctypes.c_int
+    lib.orc_wedge_closure_ranked.argtypes = [P, P, P, P, i64, P]
+    lib.orc_wedge_closure_ranked.restype = ctypes.c_int
+    lib.orc_edge_triangles.argtypes = [P, P, i64, u32, P]
+    lib.orc_edge_triangles.restype = ctypes.c_int
+    lib.orc_count_owner_sample.argtypes = [P, P, i64, ctypes.c_int, P, P]
+    lib.orc_count_owner_sample.restype = ctypes.c_int
     lib.orc_classify.argtypes = [i64] * 7
     lib.orc_classify.restype = ctypes.c_int
     lib.orc_free.argtypes = [P]
@@ -178,6 +186,60 @@ class OracleGraph:
         if rc != ORC_OK:
             raise OracleError(rc, "wedge_closure")
         return out
+
+
+    def wedge_closure_ranked(self, rank: Optional[np.ndarray], wi: np.ndarray,
+                             wj: np.ndarray) -> np.ndarray:
+        """int64[n, 21]: closure of wedges (i, j), rank[i] < rank[j], by the
+        third hyperedges k with rank[k] > rank[j] (rank None = id order).
+        Needs only the vertex lists, so it scales to graphs where
+        build_wedges/count would be too slow."""
+        wi = np.ascontiguousarray(wi, dtype=np.int32)
+        wj = np.ascontiguousarray(wj, dtype=np.int32)
+        rk = None if rank is None else np.ascontiguousarray(rank, dtype=np.int64)
+        out = np.zeros((wi.shape[0], 21), np.int64)
+        rc = self._lib.orc_wedge_closure_ranked(self._h, _ptr(rk), _ptr(wi), _ptr(wj), wi.shape[0],
+                                                _ptr(out))
+        if rc != ORC_OK:
+            raise OracleError(rc, "wedge_closure_ranked")
+        return out
+
+    def edge_triangles(self, xs: np.ndarray, edge_mask: int = 0x1FFFFE) -> np.ndarray:
+        """Per listed hyperedge: triangles containing it (patterns in edge_mask)."""
+        xs = np.ascontiguousarray(xs, dtype=np.int32)
+        out = np.zeros(xs.shape[0], np.int64)
+        rc = self._lib.orc_edge_triangles(self._h, _ptr(xs), xs.shape[0], ctypes.c_uint32(edge_mask),
+                                          _ptr(out))
+        if rc != ORC_OK:
+            raise OracleError(rc, "edge_triangles")
+        return out
+
+    def count_owner_sample(self, owners: np.ndarray, nthreads: int = 0):
+        """(H int64[21], hyperwedges closed) over the listed owners only."""
+        owners = np.ascontiguousarray(owners, dtype=np.int32)
+        if nthreads <= 0:
+            nthreads = max(1, min(16, os.cpu_count() or 1))
+        H = np.zeros(21, np.int64)
+        nw = ctypes.c_int64(0)
+        rc = self._lib.orc_count_owner_sample(self._h, _ptr(owners), owners.shape[0], int(nthreads),
+                                              _ptr(H), ctypes.byref(nw))
+        if rc != ORC_OK:
+            raise OracleError(rc, "count_owner_sample")
+        return H, int(nw.value)
+
+
+def prec_rank(offsets: np.ndarray, members: np.ndarray, num_vertices: int) -> np.ndarray:
+    """rank[x] of normalised hyperedge x in the order (delta_x, x) ascending,
+    delta_x = sum over v in e_x of (|E_v| - 1)."""
+    m = offsets.shape[0] - 1
+    dv = np.bincount(members, minlength=num_vertices).astype(np.int64)
+    owner = np.repeat(np.arange(m, dtype=np.int64), np.diff(offsets))
+    delta = np.zeros(m, np.int64)
+    np.add.at(delta, owner, dv[members] - 1)
+    order = np.lexsort((np.arange(m), delta))
+    rank = np.empty(m, np.int64)
+    rank[order] = np.arange(m)
+    return rank
 
 
 def permuted(offsets: np.ndarray, members: np.ndarray, order: np.ndarray):

@@ -197,6 +197,8 @@ void orc_get_csr(void *h, int64_t *off, int32_t *mem, int64_t *orig) {
 
 static inline int64_t esize(const orc_graph *g, int64_t x) { return g->off[x + 1] - g->off[x]; }
 
+int orc_build_vertex_lists(void *h);
+
 /* Step 1 (Algorithm 2).  E_v lists ascending by hyperedge id; for every e_i
  * the partners j > i with omega_ij, found by counting, for each v in e_i,
  * the hyperedges of E_v after e_i (the same multiset Algorithm 2's merge
@@ -204,19 +206,9 @@ static inline int64_t esize(const orc_graph *g, int64_t x) { return g->off[x + 1
 int orc_build_wedges(void *h) {
     orc_graph *g = h;
     if (g->have_wedges) return ORC_OK;
-    int64_t m = g->m, n = g->n, nnz = g->off[m];
-    g->vptr = calloc((size_t)n + 1, sizeof(int64_t));
-    g->vadj = malloc(sizeof(int32_t) * (nnz ? nnz : 1));
-    if (!g->vptr || !g->vadj) return ORC_E_OOM;
-    for (int64_t t = 0; t < nnz; t++) g->vptr[g->mem[t] + 1]++;
-    for (int64_t v = 0; v < n; v++) g->vptr[v + 1] += g->vptr[v];
-    int64_t *fill = malloc(sizeof(int64_t) * (n ? n : 1));
-    if (!fill) return ORC_E_OOM;
-    memcpy(fill, g->vptr, sizeof(int64_t) * n);
-    for (int64_t x = 0; x < m; x++)          /* ascending x => E_v ascending */
-        for (int64_t t = g->off[x]; t < g->off[x + 1]; t++)
-            g->vadj[fill[g->mem[t]]++] = (int32_t)x;
-    free(fill);
+    int64_t m = g->m;
+    int rc0 = orc_build_vertex_lists(h);
+    if (rc0 != ORC_OK) return rc0;
 
     /* count pass then fill pass, each with a dense counter + touched list */
     int32_t *cnt = calloc((size_t)(m ? m : 1), sizeof(int32_t));
@@ -487,6 +479,142 @@ int orc_count(void *h, int nthreads, uint32_t edge_mask, int64_t H_out[21], int6
     return ORC_OK;
 }
 
+/* ------------------------------------------------ on-demand neighbourhoods
+ * For graphs too large for orc_build_wedges: only the E_v lists are built,
+ * and the neighbourhood N(x) with omega of any single hyperedge is computed
+ * on demand by counting over the E_v lists of its vertices (the same
+ * counting as step 1, without the j > i restriction). */
+
+int orc_build_vertex_lists(void *h) {
+    orc_graph *g = h;
+    if (g->vptr) return ORC_OK;
+    int64_t n = g->n, m = g->m, nnz = g->off[m];
+    g->vptr = calloc((size_t)n + 1, sizeof(int64_t));
+    g->vadj = malloc(sizeof(int32_t) * (nnz ? nnz : 1));
+    int64_t *fill = malloc(sizeof(int64_t) * (n ? n : 1));
+    if (!g->vptr || !g->vadj || !fill) { free(fill); return ORC_E_OOM; }
+    for (int64_t t = 0; t < nnz; t++) g->vptr[g->mem[t] + 1]++;
+    for (int64_t v = 0; v < n; v++) g->vptr[v + 1] += g->vptr[v];
+    memcpy(fill, g->vptr, sizeof(int64_t) * n);
+    for (int64_t x = 0; x < m; x++)
+        for (int64_t t = g->off[x]; t < g->off[x + 1]; t++)
+            g->vadj[fill[g->mem[t]]++] = (int32_t)x;
+    free(fill);
+    return ORC_OK;
+}
+
+typedef struct { int32_t *nb; int32_t *om; int64_t len; } nlist;
+
+/* N(x) sorted by id, with omega; cnt must be a zeroed int32[m] scratch */
+static int neighbourhood(const orc_graph *g, int64_t x, int32_t *cnt, nlist *out) {
+    int64_t cap = 0;
+    for (int64_t t = g->off[x]; t < g->off[x + 1]; t++) {
+        int32_t v = g->mem[t];
+        cap += g->vptr[v + 1] - g->vptr[v];
+    }
+    out->nb = malloc(sizeof(int32_t) * (cap ? cap : 1));
+    out->om = malloc(sizeof(int32_t) * (cap ? cap : 1));
+    if (!out->nb || !out->om) return ORC_E_OOM;
+    int64_t nt = 0;
+    for (int64_t t = g->off[x]; t < g->off[x + 1]; t++) {
+        int32_t v = g->mem[t];
+        for (int64_t r = g->vptr[v]; r < g->vptr[v + 1]; r++) {
+            int32_t y = g->vadj[r];
+            if (y == x) continue;
+            if (cnt[y]++ == 0) out->nb[nt++] = y;
+        }
+    }
+    qsort(out->nb, (size_t)nt, sizeof(int32_t), cmp_i32);
+    for (int64_t q = 0; q < nt; q++) { out->om[q] = cnt[out->nb[q]]; cnt[out->nb[q]] = 0; }
+    out->len = nt;
+    return ORC_OK;
+}
+
+static void nfree(nlist *l) { free(l->nb); free(l->om); l->nb = l->om = NULL; }
+
+/* Per-wedge closure under an arbitrary hyperedge order: rank (int64[m], a
+ * permutation; NULL = id order).  For each wedge (i, j) with
+ * rank[i] < rank[j], out[w*21 + p] counts the third hyperedges k adjacent to
+ * both with rank[k] > rank[j], by pattern; out[w*21] is their total. */
+int orc_wedge_closure_ranked(void *h, const int64_t *rank, const int32_t *wi, const int32_t *wj,
+                             int64_t nw, int64_t *out) {
+    orc_graph *g = h;
+    int rc = orc_build_vertex_lists(h);
+    if (rc != ORC_OK) return rc;
+    int32_t *cnt = calloc((size_t)(g->m ? g->m : 1), sizeof(int32_t));
+    if (!cnt) return ORC_E_OOM;
+    for (int64_t w = 0; w < nw; w++) {
+        int64_t i = wi[w], j = wj[w];
+        int64_t *o = out + 21 * w;
+        memset(o, 0, 21 * sizeof(int64_t));
+        if (i < 0 || j < 0 || i >= g->m || j >= g->m || i == j) { free(cnt); return ORC_E_INVALID; }
+        int64_t ri = rank ? rank[i] : i, rj = rank ? rank[j] : j;
+        if (ri >= rj) { free(cnt); return ORC_E_INVALID; }
+        nlist Ni, Nj;
+        if (neighbourhood(g, i, cnt, &Ni) != ORC_OK || neighbourhood(g, j, cnt, &Nj) != ORC_OK) {
+            free(cnt); return ORC_E_OOM;
+        }
+        int64_t wij = -1;
+        for (int64_t a = 0; a < Ni.len; a++) if (Ni.nb[a] == j) { wij = Ni.om[a]; break; }
+        if (wij < 0) { nfree(&Ni); nfree(&Nj); free(cnt); return ORC_E_INVALID; }
+        int64_t a = 0, b = 0;
+        while (a < Ni.len && b < Nj.len) {
+            if (Ni.nb[a] < Nj.nb[b]) { a++; continue; }
+            if (Ni.nb[a] > Nj.nb[b]) { b++; continue; }
+            int64_t k = Ni.nb[a];
+            int64_t rk = rank ? rank[k] : k;
+            if (rk > rj) {
+                int p = classify(esize(g, i), esize(g, j), esize(g, k), wij, Ni.om[a], Nj.om[b],
+                                 triple_common(g, i, j, k));
+                o[p]++;
+                o[0]++;
+            }
+            a++; b++;
+        }
+        nfree(&Ni); nfree(&Nj);
+    }
+    free(cnt);
+    return ORC_OK;
+}
+
+/* Triangles containing each listed hyperedge x, restricted to the patterns
+ * of edge_mask: half the sum over y in N(x) of the triangles {x, y, z},
+ * z in N(x) & N(y). */
+int orc_edge_triangles(void *h, const int32_t *xs, int64_t n, uint32_t edge_mask, int64_t *out) {
+    orc_graph *g = h;
+    int rc = orc_build_vertex_lists(h);
+    if (rc != ORC_OK) return rc;
+    int32_t *cnt = calloc((size_t)(g->m ? g->m : 1), sizeof(int32_t));
+    if (!cnt) return ORC_E_OOM;
+    for (int64_t q = 0; q < n; q++) {
+        int64_t x = xs[q];
+        if (x < 0 || x >= g->m) { free(cnt); return ORC_E_INVALID; }
+        nlist Nx;
+        if (neighbourhood(g, x, cnt, &Nx) != ORC_OK) { free(cnt); return ORC_E_OOM; }
+        int64_t twice = 0;
+        for (int64_t u = 0; u < Nx.len; u++) {
+            int64_t y = Nx.nb[u];
+            nlist Ny;
+            if (neighbourhood(g, y, cnt, &Ny) != ORC_OK) { nfree(&Nx); free(cnt); return ORC_E_OOM; }
+            int64_t a = 0, b = 0;
+            while (a < Nx.len && b < Ny.len) {
+                if (Nx.nb[a] < Ny.nb[b]) { a++; continue; }
+                if (Nx.nb[a] > Ny.nb[b]) { b++; continue; }
+                int64_t z = Nx.nb[a];
+                int p = classify(esize(g, x), esize(g, y), esize(g, z), Nx.om[u], Nx.om[a], Ny.om[b],
+                                 triple_common(g, x, y, z));
+                if ((edge_mask >> p) & 1u) twice++;
+                a++; b++;
+            }
+            nfree(&Ny);
+        }
+        out[q] = twice / 2;
+        nfree(&Nx);
+    }
+    free(cnt);
+    return ORC_OK;
+}
+
 /* Per-wedge closure split by pattern for an arbitrary list of hyperwedges
  * (i, j), i<j: out[w*21 + p] = #{k > j : k adjacent to i and j, pattern p},
  * out[w*21] = their total.  Works one wedge at a time so that sampled
@@ -519,4 +647,94 @@ int orc_wedge_closure(void *h, const int32_t *wi, const int32_t *wj, int64_t nw,
         }
     }
     return ORC_OK;
+}
+
+/* The plain two-step count restricted to a list of owners, from the E_v
+ * lists alone (neighbourhoods built on demand, step 1 per owner and per
+ * partner): for each listed owner i, every hyperwedge (i, j), j > i, is
+ * closed by the k > j adjacent to both.  Used to time the oracle on a
+ * bounded sample of a large workload.  H_out[21] and the number of
+ * hyperwedges closed (*nwedges) cover the listed owners only. */
+typedef struct {
+    orc_graph *g;
+    const int32_t *owners;
+    int64_t n;
+    atomic_llong next;
+    int64_t *H;        /* nthreads x 21 */
+    int64_t *nw;       /* nthreads */
+    atomic_int err;
+} sample_job;
+
+typedef struct { sample_job *job; int tid; } sample_arg;
+
+static void *sample_worker(void *p) {
+    sample_arg *arg = p;
+    sample_job *job = arg->job;
+    orc_graph *g = job->g;
+    int64_t *H = job->H + 21 * arg->tid;
+    int32_t *cnt = calloc((size_t)(g->m ? g->m : 1), sizeof(int32_t));
+    if (!cnt) { atomic_store(&job->err, ORC_E_OOM); return NULL; }
+    for (;;) {
+        int64_t q = atomic_fetch_add(&job->next, 1);
+        if (q >= job->n) break;
+        int64_t i = job->owners[q];
+        nlist Ni;
+        if (neighbourhood(g, i, cnt, &Ni) != ORC_OK) { atomic_store(&job->err, ORC_E_OOM); break; }
+        for (int64_t u = 0; u < Ni.len; u++) {
+            int64_t j = Ni.nb[u];
+            if (j <= i) continue;
+            job->nw[arg->tid]++;
+            nlist Nj;
+            if (neighbourhood(g, j, cnt, &Nj) != ORC_OK) { atomic_store(&job->err, ORC_E_OOM); break; }
+            int64_t a = u + 1, b = 0;
+            while (b < Nj.len && Nj.nb[b] <= j) b++;
+            while (a < Ni.len && b < Nj.len) {
+                if (Ni.nb[a] < Nj.nb[b]) { a++; continue; }
+                if (Ni.nb[a] > Nj.nb[b]) { b++; continue; }
+                int64_t k = Ni.nb[a];
+                int p = classify(esize(g, i), esize(g, j), esize(g, k), Ni.om[u], Ni.om[a], Nj.om[b],
+                                 triple_common(g, i, j, k));
+                H[p]++;
+                a++; b++;
+            }
+            nfree(&Nj);
+        }
+        nfree(&Ni);
+    }
+    free(cnt);
+    return NULL;
+}
+
+int orc_count_owner_sample(void *h, const int32_t *owners, int64_t n, int nthreads, int64_t H_out[21],
+                           int64_t *nwedges) {
+    orc_graph *g = h;
+    int rc = orc_build_vertex_lists(h);
+    if (rc != ORC_OK) return rc;
+    if (nthreads < 1) nthreads = 1;
+    for (int64_t q = 0; q < n; q++)
+        if (owners[q] < 0 || owners[q] >= g->m) return ORC_E_INVALID;
+    sample_job job;
+    job.g = g; job.owners = owners; job.n = n;
+    atomic_init(&job.next, 0);
+    atomic_init(&job.err, ORC_OK);
+    job.H = calloc((size_t)nthreads * 21, sizeof(int64_t));
+    job.nw = calloc((size_t)nthreads, sizeof(int64_t));
+    pthread_t *th = malloc(sizeof(pthread_t) * nthreads);
+    sample_arg *args = malloc(sizeof(sample_arg) * nthreads);
+    if (!job.H || !job.nw || !th || !args) { free(job.H); free(job.nw); free(th); free(args); return ORC_E_OOM; }
+    for (int t = 0; t < nthreads; t++) {
+        args[t].job = &job; args[t].tid = t;
+        pthread_create(&th[t], NULL, sample_worker, &args[t]);
+    }
+    for (int t = 0; t < nthreads; t++) pthread_join(th[t], NULL);
+    memset(H_out, 0, 21 * sizeof(int64_t));
+    *nwedges = 0;
+    for (int t = 0; t < nthreads; t++) {
+        for (int p = 1; p <= 20; p++) H_out[p] += job.H[21 * t + p];
+        *nwedges += job.nw[t];
+    }
+    for (int p = 1; p <= 20; p++) H_out[0] += H_out[p];
+    rc = atomic_load(&job.err);
+    free(job.H); free(job.nw); free(th); free(args);
+    return rc;
 }

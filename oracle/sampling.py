@@ -1,0 +1,103 @@
+"""Oracle side of hyperwedge sampling -- test infrastructure only.
+
+Philox4x32-10 counter-based generator, written from its published
+definition (Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as
+easy as 1, 2, 3", SC 2011): a 4x32-bit counter and 2x32-bit key, ten rounds
+of two 32x32->64 multiplications by 0xD2511F53 and 0xCD9E8D57 with the key
+bumped by the Weyl constants 0x9E3779B9 and 0xBB67AE85 between rounds.
+
+The estimators follow Algorithm 6 with sigma = 1 (hyperwedges drawn with
+replacement, each closed with the third hyperedges that come after it, the
+sum scaled by |wedges| / samples), unbiased by Lemma 4.1, and its
+importance-sampling generalisation (each closure divided by the realised
+draw probability).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+M0 = 0xD2511F53
+M1 = 0xCD9E8D57
+W0 = 0x9E3779B9
+W1 = 0xBB67AE85
+MASK = 0xFFFFFFFF
+
+
+def philox4x32_10(ctr, key):
+    """One block: ctr = 4 uint32 (numpy arrays broadcast), key = 2 uint32."""
+    x0, x1, x2, x3 = (np.asarray(c, dtype=np.uint64) for c in ctr)
+    k0, k1 = (np.asarray(k, dtype=np.uint64) for k in key)
+    for r in range(10):
+        if r:
+            k0 = (k0 + W0) & MASK
+            k1 = (k1 + W1) & MASK
+        p0 = x0 * np.uint64(M0)
+        p1 = x2 * np.uint64(M1)
+        hi0, lo0 = p0 >> np.uint64(32), p0 & np.uint64(MASK)
+        hi1, lo1 = p1 >> np.uint64(32), p1 & np.uint64(MASK)
+        x0, x1, x2, x3 = (hi1 ^ x1 ^ k0) & MASK, lo1, (hi0 ^ x3 ^ k1) & MASK, lo0
+    return x0, x1, x2, x3
+
+
+def draws_u64(seed: int, stream: int, n: int, start: int = 0) -> np.ndarray:
+    """n 64-bit uniform words: counter (t lo, t hi, stream, 0), key = seed."""
+    t = np.arange(start, start + n, dtype=np.uint64)
+    ctr = (t & np.uint64(MASK), t >> np.uint64(32), np.full(n, stream, np.uint64), np.zeros(n, np.uint64))
+    key = (np.uint64(seed & MASK), np.uint64((seed >> 32) & MASK))
+    x0, x1, _, _ = philox4x32_10(ctr, key)
+    return (x1 << np.uint64(32)) | x0
+
+
+def uniform_indices(seed: int, stream: int, n: int, N: int) -> np.ndarray:
+    """floor(u * N / 2^64) for the 64-bit words u -- exact integer arithmetic."""
+    u = draws_u64(seed, stream, n)
+    hi = u >> np.uint64(32)
+    lo = u & np.uint64(MASK)
+    N = np.uint64(N)
+    # (u * N) >> 64 with u = hi*2^32 + lo, N < 2^63
+    nh = N >> np.uint64(32)
+    nl = N & np.uint64(MASK)
+    ll = lo * nl
+    lh = lo * nh
+    hl = hi * nl
+    hh = hi * nh
+    mid = (ll >> np.uint64(32)) + (lh & np.uint64(MASK)) + (hl & np.uint64(MASK))
+    return (hh + (lh >> np.uint64(32)) + (hl >> np.uint64(32)) + (mid >> np.uint64(32))).astype(np.int64)
+
+
+def uniform01(seed: int, stream: int, n: int) -> np.ndarray:
+    """Doubles in [0, 1): the top 53 bits of each 64-bit word."""
+    return (draws_u64(seed, stream, n) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def prec_wedge_order(rank: np.ndarray, wi: np.ndarray, wj: np.ndarray):
+    """Hyperwedges oriented from the earlier to the later hyperedge in the
+    order `rank`, listed by (rank of the earlier, rank of the later)."""
+    lo = np.where(rank[wi] < rank[wj], wi, wj)
+    hi = np.where(rank[wi] < rank[wj], wj, wi)
+    order = np.lexsort((rank[hi], rank[lo]))
+    return lo[order], hi[order]
+
+
+def uniform_estimate(closures: np.ndarray, num_wedges: int):
+    """Algorithm 6 with sigma = 1.  closures: int64[n, 21] per drawn wedge.
+    Returns (estimate[21], standard error[21])."""
+    n = closures.shape[0]
+    sums = closures.sum(axis=0)
+    est = sums.astype(np.float64) * float(num_wedges) / float(n)
+    y = closures.astype(np.float64) * float(num_wedges)
+    var = (y ** 2).sum(axis=0) - n * (est ** 2)
+    se = np.sqrt(np.maximum(var, 0.0) / (n * max(n - 1, 1)))
+    return est, se
+
+
+def relative_error(est: np.ndarray, exact: np.ndarray):
+    """Mean of |H - est| / H over the patterns with H > 0 (the error metric of
+    Section 6.3, restricted to patterns that occur), and the per-pattern
+    relative errors."""
+    H = exact[1:].astype(np.float64)
+    E = est[1:]
+    nz = H > 0
+    rel = np.full(20, np.nan)
+    rel[nz] = np.abs(H[nz] - E[nz]) / H[nz]
+    return float(np.nanmean(rel)) if nz.any() else 0.0, rel

@@ -1,0 +1,234 @@
+// C ABI of libhtri: argument checks, status codes, host <-> device copies.
+#include <mutex>
+
+#include "internal.hpp"
+
+namespace {
+
+std::mutex g_err_mu;
+std::string g_load_err;
+
+template <typename F>
+htri_status run(htri::Graph *g, F &&fn) {
+    try {
+        fn();
+        return HTRI_OK;
+    } catch (const htri::Error &e) {
+        if (g) g->err = e.msg;
+        else {
+            std::lock_guard<std::mutex> lk(g_err_mu);
+            g_load_err = e.msg;
+        }
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        if (g) g->err = "host allocation failed";
+        return HTRI_E_OOM;
+    } catch (const std::exception &e) {
+        if (g) g->err = e.what();
+        return HTRI_E_INVALID;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *htri_status_string(htri_status s) {
+    switch (s) {
+        case HTRI_OK: return "ok";
+        case HTRI_E_INVALID: return "invalid argument";
+        case HTRI_E_RANGE: return "vertex id out of range";
+        case HTRI_E_EMPTY_EDGE: return "empty hyperedge";
+        case HTRI_E_DUPLICATE_EDGE: return "duplicate hyperedge";
+        case HTRI_E_OOM: return "out of device memory";
+        case HTRI_E_DEVICE: return "HIP runtime error";
+        case HTRI_E_OVERFLOW: return "count overflow";
+        case HTRI_E_STATE: return "call order";
+        case HTRI_E_UNSUPPORTED: return "unsupported size";
+    }
+    return "unknown status";
+}
+
+const char *htri_last_error(const htri_graph *h) {
+    if (h) return h->g.err.c_str();
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    return g_load_err.c_str();
+}
+
+htri_status htri_graph_load(const int64_t *edge_offsets, int64_t num_edges, const int32_t *members,
+                            int32_t num_vertices, uint32_t flags, const htri_allocator *alloc, void *stream,
+                            htri_graph **out) {
+    if (!out) return HTRI_E_INVALID;
+    *out = nullptr;
+    if (!edge_offsets || num_edges < 0 || num_vertices < 0 || (!members && num_edges > 0)) {
+        std::lock_guard<std::mutex> lk(g_err_mu);
+        g_load_err = "null pointer or negative size";
+        return HTRI_E_INVALID;
+    }
+    if (flags & ~(HTRI_DEDUPE_EDGES | HTRI_INPUT_ON_DEVICE | HTRI_ORDER_INPUT)) {
+        std::lock_guard<std::mutex> lk(g_err_mu);
+        g_load_err = "unknown flag";
+        return HTRI_E_INVALID;
+    }
+    if (alloc && (!alloc->alloc || !alloc->free)) {
+        std::lock_guard<std::mutex> lk(g_err_mu);
+        g_load_err = "allocator without alloc/free";
+        return HTRI_E_INVALID;
+    }
+    htri_graph *h = nullptr;
+    try {
+        h = new htri_graph();
+    } catch (...) {
+        return HTRI_E_OOM;
+    }
+    h->g.stream = (hipStream_t)stream;
+    h->g.al.stream = (hipStream_t)stream;
+    if (alloc) {
+        h->g.al.user = *alloc;
+        h->g.al.has_user = true;
+    }
+    htri_status st = run(nullptr, [&] {
+        htri::graph_load(h->g, edge_offsets, num_edges, members, num_vertices, flags);
+    });
+    if (st != HTRI_OK) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return HTRI_OK;
+}
+
+htri_status htri_graph_info(const htri_graph *h, int64_t out[4]) {
+    if (!h || !out) return HTRI_E_INVALID;
+    out[0] = h->g.m;
+    out[1] = h->g.removed;
+    out[2] = h->g.nnz;
+    out[3] = h->g.n;
+    return HTRI_OK;
+}
+
+htri_status htri_graph_edge_map(const htri_graph *h, int64_t *new_to_input) {
+    if (!h || (!new_to_input && h->g.m > 0)) return HTRI_E_INVALID;
+    if (h->g.m) std::memcpy(new_to_input, h->g.norm_to_input.data(), sizeof(int64_t) * h->g.m);
+    return HTRI_OK;
+}
+
+htri_status htri_graph_csr(const htri_graph *hc, int64_t *offsets, int32_t *members) {
+    htri_graph *h = const_cast<htri_graph *>(hc);
+    if (!h || !offsets || (!members && h->g.nnz > 0)) return HTRI_E_INVALID;
+    return run(&h->g, [&] {
+        htri::Graph &g = h->g;
+        HTRI_HIP(hipMemcpyAsync(offsets, g.eptr_n.p, sizeof(int64_t) * (g.m + 1), hipMemcpyDeviceToHost, g.stream));
+        if (g.nnz)
+            HTRI_HIP(hipMemcpyAsync(members, g.emem_n.p, sizeof(int32_t) * g.nnz, hipMemcpyDeviceToHost, g.stream));
+        HTRI_HIP(hipStreamSynchronize(g.stream));
+    });
+}
+
+htri_status htri_build_wedges(htri_graph *h, int64_t summary[6]) {
+    if (!h) return HTRI_E_INVALID;
+    htri_status st = HTRI_OK;
+    if (!h->g.have_wedges) st = run(&h->g, [&] { htri::build_wedges(h->g); });
+    if (st == HTRI_OK && summary) std::memcpy(summary, h->g.summary, sizeof(int64_t) * 6);
+    return st;
+}
+
+htri_status htri_clear_wedges(htri_graph *h) {
+    if (!h) return HTRI_E_INVALID;
+    return run(&h->g, [&] {
+        htri::Graph &g = h->g;
+        HTRI_HIP(hipStreamSynchronize(g.stream));
+        g.fptr.reset();
+        g.fadj.reset();
+        g.mptr.reset();
+        g.fmask.reset();
+        g.indeg.reset();
+        g.nw = 0;
+        g.have_wedges = false;
+    });
+}
+
+htri_status htri_closure_stats(const htri_graph *h, int64_t out[5]) {
+    if (!h || !out) return HTRI_E_INVALID;
+    std::memcpy(out, h->g.cstats, sizeof(int64_t) * 5);
+    return HTRI_OK;
+}
+
+htri_status htri_get_wedges(const htri_graph *hc, int32_t *src, int32_t *dst, int32_t *omega) {
+    htri_graph *h = const_cast<htri_graph *>(hc);
+    if (!h || (h->g.nw > 0 && (!src || !dst))) return HTRI_E_INVALID;
+    if (!h->g.have_wedges) {
+        h->g.err = "htri_build_wedges has not run";
+        return HTRI_E_STATE;
+    }
+    return run(&h->g, [&] {
+        htri::Graph &g = h->g;
+        std::vector<int64_t> fptr((size_t)g.m + 1);
+        std::vector<uint32_t> fadj((size_t)g.nw);
+        std::vector<int32_t> nor((size_t)g.m);
+        HTRI_HIP(hipMemcpyAsync(fptr.data(), g.fptr.p, sizeof(int64_t) * (g.m + 1), hipMemcpyDeviceToHost, g.stream));
+        if (g.nw) HTRI_HIP(hipMemcpyAsync(fadj.data(), g.fadj.p, sizeof(uint32_t) * g.nw, hipMemcpyDeviceToHost, g.stream));
+        if (g.m) HTRI_HIP(hipMemcpyAsync(nor.data(), g.norm_of_rank.p, sizeof(int32_t) * g.m, hipMemcpyDeviceToHost, g.stream));
+        HTRI_HIP(hipStreamSynchronize(g.stream));
+        const uint32_t wmask = (1u << g.wbits) - 1;
+        for (int64_t r = 0; r < g.m; r++)
+            for (int64_t e = fptr[r]; e < fptr[r + 1]; e++) {
+                src[e] = nor[r];
+                dst[e] = nor[fadj[e] >> g.wbits];
+                if (omega) omega[e] = (int32_t)(fadj[e] & wmask);
+            }
+    });
+}
+
+htri_status htri_count_patterns(htri_graph *h, uint32_t per_edge_pattern_mask, int64_t counts[21],
+                                int64_t *per_edge, int32_t *per_wedge, uint32_t out_flags) {
+    if (!h || !counts) return HTRI_E_INVALID;
+    if (out_flags & ~HTRI_OUTPUT_ON_DEVICE) return HTRI_E_INVALID;
+    if (!h->g.have_wedges) {
+        h->g.err = "htri_build_wedges has not run";
+        return HTRI_E_STATE;
+    }
+    uint32_t mask = per_edge_pattern_mask ? (per_edge_pattern_mask & 0x1FFFFEu) : 0x1FFFFEu;
+    return run(&h->g, [&] {
+        htri::Graph &g = h->g;
+        const bool dev = out_flags & HTRI_OUTPUT_ON_DEVICE;
+        htri::DBuf<int64_t> t_tmp;
+        htri::DBuf<uint32_t> cw_tmp;
+        uint64_t *t_dev = nullptr;
+        uint32_t *cw_dev = nullptr;
+        if (per_edge) {
+            if (dev) t_dev = (uint64_t *)per_edge;
+            else { t_tmp.alloc(g.al, g.m); t_dev = (uint64_t *)t_tmp.p; }
+        }
+        if (per_wedge) {
+            if (dev) cw_dev = (uint32_t *)per_wedge;
+            else { cw_tmp.alloc(g.al, g.nw); cw_dev = cw_tmp.p; }
+        }
+        int64_t c[21];
+        htri::count_patterns(g, mask, c, t_dev, cw_dev);
+        if (per_edge && !dev && g.m)
+            HTRI_HIP(hipMemcpyAsync(per_edge, t_dev, sizeof(int64_t) * g.m, hipMemcpyDeviceToHost, g.stream));
+        if (per_wedge && !dev && g.nw)
+            HTRI_HIP(hipMemcpyAsync(per_wedge, cw_dev, sizeof(int32_t) * g.nw, hipMemcpyDeviceToHost, g.stream));
+        HTRI_HIP(hipStreamSynchronize(g.stream));
+        std::memcpy(counts, c, sizeof(c));
+    });
+}
+
+htri_status htri_last_timings(const htri_graph *h, double ms[4]) {
+    if (!h || !ms) return HTRI_E_INVALID;
+    ms[0] = h->g.tm.wedges_ms;
+    ms[1] = h->g.tm.schedule_ms;
+    ms[2] = h->g.tm.closure_ms;
+    ms[3] = h->g.tm.reduce_ms;
+    return HTRI_OK;
+}
+
+void htri_graph_free(htri_graph *h) {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->g.stream);
+    delete h;
+}
+
+}  // extern "C"

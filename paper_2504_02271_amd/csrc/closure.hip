@@ -1,0 +1,636 @@
+// Step 2 of the two-step framework: close every hyperwedge and classify the
+// hyper-triangle (Algorithm 3 for the intersection-only class, Algorithm 5
+// for the classes with inclusion hyperwedges, combined over all patterns as
+// the paper's Exact-adv).
+//
+// Orientation: hyperedges are ranked by prec; the forward list N+(r) holds
+// the later neighbours of r, sorted.  A triangle r < j < k is found exactly
+// once, by owner r, as a k that lies in both N+(r) and N+(j).
+//
+// Work decomposition (MI355X): an item is (owner r, a chunk of at most CAP
+// consecutive entries of N+(r), a piece of at most 256 partners j of r).
+// The chunk goes into an LDS open-addressing hash; every partner's N+(j),
+// restricted to the chunk's rank range, is streamed from HBM with coalesced
+// loads and probed against the hash.  A hit is classified from the sizes,
+// the three omegas and g = popcount(Omega_rj & Omega_rk) (both masks are
+// over e_r's member positions) through a 128-entry region-emptiness table.
+// Persistent blocks pull items from a queue; pattern counts stay in per-lane
+// LDS counters and leave the kernel as one partial per block.
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace htri {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kJPiece = 256;            // partners per item (one thread each)
+constexpr int kMaskWordsMax = 4;
+constexpr uint64_t kEmpty = ~0ull;
+
+struct Item {
+    int32_t r, cb, ce, jb, je;
+};
+
+__host__ __device__ __forceinline__ int mask_words(int size) {
+    return size <= 32 * kMaskWordsMax ? (size + 31) / 32 : 0;
+}
+
+__device__ __forceinline__ uint32_t hslot(uint32_t k, int hbits) {
+    return (k * 0x9E3779B1u) >> (32 - hbits);
+}
+
+// first index in [a, b) whose entry's rank is >= key
+__device__ __forceinline__ int64_t lower_rank(const uint32_t *fadj, int64_t a, int64_t b, uint32_t key,
+                                              int wbits) {
+    while (a < b) {
+        int64_t mid = a + ((b - a) >> 1);
+        if ((fadj[mid] >> wbits) < key) a = mid + 1; else b = mid;
+    }
+    return a;
+}
+
+// |e_r & e_j & e_k| by a three-way merge of sorted member lists (hyperedges
+// too large for stored masks)
+__device__ int triple_common(const int64_t *eptr, const int32_t *emem, int32_t r, int32_t j, int32_t k) {
+    int64_t a = eptr[r], ae = eptr[r + 1], b = eptr[j], be = eptr[j + 1], c = eptr[k], ce = eptr[k + 1];
+    int cnt = 0;
+    while (a < ae && b < be && c < ce) {
+        int32_t x = emem[a], y = emem[b], z = emem[c];
+        if (x == y && y == z) { cnt++; a++; b++; c++; continue; }
+        int32_t mx = x > y ? x : y;
+        mx = mx > z ? mx : z;
+        if (x < mx) a++;
+        if (y < mx) b++;
+        if (z < mx) c++;
+    }
+    return cnt;
+}
+
+__device__ __forceinline__ uint32_t region_mask(int si, int sj, int sk, int wij, int wik, int wjk, int g) {
+    int a = si - wij - wik + g, b = sj - wij - wjk + g, c = sk - wik - wjk + g;
+    int d = wij - g, e = wjk - g, f = wik - g;
+    return (uint32_t)(a > 0) | ((uint32_t)(b > 0) << 1) | ((uint32_t)(c > 0) << 2) | ((uint32_t)(d > 0) << 3) |
+           ((uint32_t)(e > 0) << 4) | ((uint32_t)(f > 0) << 5) | ((uint32_t)(g > 0) << 6);
+}
+
+struct CloseArgs {
+    const Item *items;
+    int64_t nitems;
+    unsigned int *queue;            // item counter
+    const int64_t *fptr;
+    const uint32_t *fadj;
+    const int64_t *mptr;
+    const uint32_t *fmask;
+    const int32_t *esize;
+    const int64_t *eptr;
+    const int32_t *emem;
+    int wbits;
+    uint32_t emask;                 // patterns counted into per-edge counts
+    const uint8_t *lut;             // device copy of the 128-entry table
+    uint32_t *cwj;                  // per-wedge j-role count, all patterns (or null)
+    uint32_t *cwjm;                 // per-wedge j-role count, masked (or null)
+    uint32_t *cwkm;                 // per-wedge k-role count, masked (or null)
+    unsigned long long *partials;   // [gridDim.x][22]: patterns, then probes
+};
+
+template <int CAP, bool PER_EDGE, bool PER_WEDGE>
+__global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
+    constexpr int HMAX = 2 * CAP;
+    __shared__ uint64_t tab[HMAX];
+    __shared__ uint32_t ent_size[CAP];
+    __shared__ uint32_t ent_mask[CAP * kMaskWordsMax];
+    __shared__ uint32_t ent_ck[PER_EDGE ? CAP : 1];
+    __shared__ int64_t seg_pre[kJPiece + 1];
+    __shared__ int64_t seg_src[kJPiece];
+    __shared__ uint32_t seg_size[kJPiece];
+    __shared__ uint32_t seg_om[kJPiece];
+    __shared__ uint32_t seg_mask[kJPiece * kMaskWordsMax];
+    __shared__ uint32_t seg_cj[kJPiece];
+    __shared__ uint32_t seg_cjm[PER_EDGE ? kJPiece : 1];
+    __shared__ uint32_t pcnt[21][kBlock];
+    __shared__ unsigned long long pacc[21];
+    __shared__ uint8_t lut[128];
+    __shared__ int64_t sh_item;
+    __shared__ int64_t sh_scan[kBlock / kWave + 1];
+
+    const int tid = threadIdx.x;
+    const uint32_t wmask = (1u << A.wbits) - 1;
+    for (int p = 0; p < 21; p++) pcnt[p][tid] = 0;
+    if (tid < 21) pacc[tid] = 0;
+    if (tid < 128) lut[tid] = A.lut[tid];
+    uint64_t block_probes = 0;
+    unsigned long long all_probes = 0;
+
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) {
+            unsigned int c = atomicAdd(A.queue, 1u);
+            sh_item = (int64_t)c < A.nitems ? A.nitems - 1 - (int64_t)c : -1;
+        }
+        __syncthreads();
+        const int64_t it = sh_item;
+        if (it < 0) break;
+        const Item item = A.items[it];
+        const int32_t r = item.r;
+        const int64_t base = A.fptr[r];
+        const int32_t d = (int32_t)(A.fptr[r + 1] - base);
+        const bool single = item.cb == 0 && item.ce == d && item.jb == 0 && item.je == d - 1;
+        const int si = A.esize[r];
+        const int W = mask_words(si);
+        const int64_t mbase = A.mptr[r];
+        const int cl = item.ce - item.cb;
+        int hbits = 6;
+        while ((1 << hbits) < 2 * cl) hbits++;
+        const int H = 1 << hbits;
+        const uint32_t lo = A.fadj[base + item.cb] >> A.wbits;
+        const uint32_t hi = A.fadj[base + item.ce - 1] >> A.wbits;
+
+        for (int s = tid; s < H; s += kBlock) tab[s] = kEmpty;
+        __syncthreads();
+        // stage the chunk
+        for (int q = tid; q < cl; q += kBlock) {
+            uint32_t ent = A.fadj[base + item.cb + q];
+            uint32_t k = ent >> A.wbits;
+            ent_size[q] = (uint32_t)A.esize[k];
+            for (int w = 0; w < W; w++) ent_mask[q * kMaskWordsMax + w] = A.fmask[mbase + (int64_t)(item.cb + q) * W + w];
+            if (PER_EDGE) ent_ck[q] = 0;
+            uint64_t v = ((uint64_t)q << 32) | ent;
+            uint32_t slot = hslot(k, hbits);
+            while (atomicCAS((unsigned long long *)&tab[slot], (unsigned long long)kEmpty,
+                             (unsigned long long)v) != kEmpty)
+                slot = (slot + 1) & (H - 1);
+        }
+        // partner segments
+        const int nseg = item.je - item.jb;
+        int64_t len = 0;
+        if (tid < nseg) {
+            const int pj = item.jb + tid;
+            const uint32_t jent = A.fadj[base + pj];
+            const uint32_t j = jent >> A.wbits;
+            int64_t a = A.fptr[j], b = A.fptr[j + 1];
+            if (!single) {
+                a = lower_rank(A.fadj, a, b, lo, A.wbits);
+                b = lower_rank(A.fadj, a, b, hi + 1, A.wbits);
+            }
+            len = b - a;
+            seg_src[tid] = a;
+            seg_size[tid] = (uint32_t)A.esize[j];
+            seg_om[tid] = jent & wmask;
+            for (int w = 0; w < W; w++) seg_mask[tid * kMaskWordsMax + w] = A.fmask[mbase + (int64_t)pj * W + w];
+            seg_cj[tid] = 0;
+            if (PER_EDGE) seg_cjm[tid] = 0;
+        }
+        // exclusive scan of segment lengths
+        {
+            const int lane = tid & (kWave - 1), wave = tid / kWave;
+            int64_t incl = len;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                int64_t u = __shfl_up(incl, o, kWave);
+                if (lane >= o) incl += u;
+            }
+            if (lane == kWave - 1) sh_scan[wave] = incl;
+            __syncthreads();
+            if (tid == 0) {
+                int64_t run = 0;
+                for (int w = 0; w < kBlock / kWave; w++) {
+                    int64_t c = sh_scan[w];
+                    sh_scan[w] = run;
+                    run += c;
+                }
+                sh_scan[kBlock / kWave] = run;
+            }
+            __syncthreads();
+            seg_pre[tid] = sh_scan[wave] + incl - len;
+            if (tid == 0) seg_pre[kBlock] = sh_scan[kBlock / kWave];
+        }
+        __syncthreads();
+        const int64_t total = seg_pre[kBlock];
+        block_probes += (uint64_t)total;
+        all_probes += (unsigned long long)total;
+
+        // stream the partner lists
+        int q = -1;
+        int sj = 0, wij = 0;
+        uint32_t mj[kMaskWordsMax] = {0, 0, 0, 0};
+        int64_t src = 0;
+        uint32_t cj = 0, cjm = 0;
+        int32_t jrank = 0;
+        for (int64_t f = tid; f < total; f += kBlock) {
+            if (q < 0 || seg_pre[q + 1] <= f) {
+                if (q >= 0) {
+                    if (PER_WEDGE && cj) atomicAdd(&seg_cj[q], cj);
+                    if (PER_EDGE && cjm) atomicAdd(&seg_cjm[q], cjm);
+                }
+                cj = cjm = 0;
+                // upper bound of f in seg_pre[q+1 .. nseg]
+                int lo_s = q < 0 ? 0 : q + 1, hi_s = nseg;
+                while (lo_s < hi_s) {
+                    int mid = (lo_s + hi_s) >> 1;
+                    if (seg_pre[mid + 1] <= f) lo_s = mid + 1; else hi_s = mid;
+                }
+                q = lo_s;
+                sj = (int)seg_size[q];
+                wij = (int)seg_om[q];
+#pragma unroll
+                for (int w = 0; w < kMaskWordsMax; w++) mj[w] = w < W ? seg_mask[q * kMaskWordsMax + w] : 0u;
+                src = seg_src[q] - seg_pre[q];
+                jrank = (int32_t)(A.fadj[base + item.jb + q] >> A.wbits);
+            }
+            const uint32_t ent = A.fadj[src + f];
+            const uint32_t k = ent >> A.wbits;
+            uint32_t slot = hslot(k, hbits);
+            uint64_t v;
+            for (;;) {
+                v = tab[slot];
+                if (v == kEmpty || ((uint32_t)v >> A.wbits) == k) break;
+                slot = (slot + 1) & (H - 1);
+            }
+            if (v != kEmpty) {
+                const uint32_t pos = (uint32_t)(v >> 32);
+                const int wik = (int)((uint32_t)v & wmask);
+                const int wjk = (int)(ent & wmask);
+                const int sk = (int)ent_size[pos];
+                int g;
+                if (W > 0) {
+                    g = 0;
+#pragma unroll
+                    for (int w = 0; w < kMaskWordsMax; w++)
+                        if (w < W) g += __popc(mj[w] & ent_mask[pos * kMaskWordsMax + w]);
+                } else {
+                    g = triple_common(A.eptr, A.emem, r, jrank, (int32_t)k);
+                }
+                const uint32_t p = lut[region_mask(si, sj, sk, wij, wik, wjk, g)];
+                pcnt[p][tid] += 1;
+                cj++;
+                if (PER_EDGE && ((A.emask >> p) & 1u)) {
+                    cjm++;
+                    atomicAdd(&ent_ck[pos], 1u);
+                }
+            }
+        }
+        if (q >= 0) {
+            if (PER_WEDGE && cj) atomicAdd(&seg_cj[q], cj);
+            if (PER_EDGE && cjm) atomicAdd(&seg_cjm[q], cjm);
+        }
+        __syncthreads();
+        // per-wedge counters
+        if (PER_WEDGE || PER_EDGE) {
+            if (tid < nseg) {
+                const int64_t e = base + item.jb + tid;
+                if (single) {
+                    if (PER_WEDGE) A.cwj[e] = seg_cj[tid];
+                    if (PER_EDGE) A.cwjm[e] = seg_cjm[tid];
+                } else {
+                    if (PER_WEDGE && seg_cj[tid]) atomicAdd(&A.cwj[e], seg_cj[tid]);
+                    if (PER_EDGE && seg_cjm[tid]) atomicAdd(&A.cwjm[e], seg_cjm[tid]);
+                }
+            }
+            if (PER_EDGE) {
+                for (int qq = tid; qq < cl; qq += kBlock) {
+                    const int64_t e = base + item.cb + qq;
+                    if (single) A.cwkm[e] = ent_ck[qq];
+                    else if (ent_ck[qq]) atomicAdd(&A.cwkm[e], ent_ck[qq]);
+                }
+            }
+        }
+        // keep the per-lane 32-bit counters far from overflow
+        if (block_probes > (1ull << 31)) {
+            __syncthreads();
+            if (tid < 21) {
+                unsigned long long s = 0;
+                for (int l = 0; l < kBlock; l++) s += pcnt[tid][l];
+                pacc[tid] += s;
+            }
+            __syncthreads();
+            for (int p = 0; p < 21; p++) pcnt[p][tid] = 0;
+            block_probes = 0;
+        }
+    }
+    __syncthreads();
+    if (tid < 21) {
+        unsigned long long s = pacc[tid];
+        for (int l = 0; l < kBlock; l++) s += pcnt[tid][l];
+        A.partials[(int64_t)blockIdx.x * 22 + tid] = s;
+    }
+    if (tid == 0) A.partials[(int64_t)blockIdx.x * 22 + 21] = all_probes;
+}
+
+// number of items per owner
+template <int CAP>
+__global__ void k_item_counts(const int64_t *fptr, int64_t m, int64_t *cnt) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        int64_t d = fptr[r + 1] - fptr[r];
+        int64_t c = 0;
+        if (d >= 2) {
+            for (int64_t cb = 0; cb < d; cb += CAP) {
+                int64_t ce = cb + CAP < d ? cb + CAP : d;
+                int64_t jend = ce - 1;
+                c += (jend + kJPiece - 1) / kJPiece;
+            }
+        }
+        cnt[r] = c;
+    }
+}
+
+template <int CAP>
+__global__ void k_item_fill(const int64_t *fptr, int64_t m, const int64_t *ioff, Item *items) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        int64_t d = fptr[r + 1] - fptr[r];
+        if (d < 2) continue;
+        int64_t o = ioff[r];
+        for (int64_t cb = 0; cb < d; cb += CAP) {
+            int64_t ce = cb + CAP < d ? cb + CAP : d;
+            int64_t jend = ce - 1;
+            for (int64_t jb = 0; jb < jend; jb += kJPiece) {
+                Item it;
+                it.r = (int32_t)r;
+                it.cb = (int32_t)cb;
+                it.ce = (int32_t)ce;
+                it.jb = (int32_t)jb;
+                it.je = (int32_t)(jb + kJPiece < jend ? jb + kJPiece : jend);
+                items[o++] = it;
+            }
+        }
+    }
+}
+
+// counts[0..20] patterns (counts[0] = total), counts[21] = entries probed
+__global__ void k_reduce_partials(const unsigned long long *partials, int nblocks, long long *counts) {
+    __shared__ unsigned long long s[22];
+    if (threadIdx.x < 22) {
+        unsigned long long acc = 0;
+        for (int b = 0; b < nblocks; b++) acc += partials[(int64_t)b * 22 + threadIdx.x];
+        s[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long tot = 0;
+        for (int p = 1; p <= 20; p++) tot += s[p];
+        counts[0] = (long long)tot;
+        for (int p = 1; p <= 20; p++) counts[p] = (long long)s[p];
+        counts[21] = (long long)s[21];
+    }
+}
+
+// S = sum over hyperwedges (r, j) of |N+(j)|
+__global__ void k_stream_size(const int64_t *fptr, const uint32_t *fadj, int64_t nw, int wbits,
+                              unsigned long long *S) {
+    __shared__ unsigned long long sh[256];
+    unsigned long long acc = 0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nw;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t j = fadj[e] >> wbits;
+        acc += (unsigned long long)(fptr[j + 1] - fptr[j]);
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(S, sh[0]);
+}
+
+// per-hyperedge counts from the per-wedge role counters
+__global__ void k_edge_counts(const int64_t *fptr, const uint32_t *fadj, int64_t m, int wbits,
+                              const uint32_t *cwjm, const uint32_t *cwkm, unsigned long long *t) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        unsigned long long own = 0;
+        for (int64_t e = fptr[r]; e < fptr[r + 1]; e++) {
+            uint32_t x = fadj[e] >> wbits;
+            uint32_t c = cwjm[e] + cwkm[e];
+            if (c) atomicAdd(&t[x], (unsigned long long)c);
+            own += cwjm[e];
+        }
+        if (own) atomicAdd(&t[r], own);
+    }
+}
+
+__global__ void k_rank_to_norm_u64(const unsigned long long *t, const int32_t *norm_of_rank, int64_t m,
+                                   int64_t *out) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
+         r += (int64_t)gridDim.x * blockDim.x)
+        out[norm_of_rank[r]] = (int64_t)t[r];
+}
+
+template <int CAP, bool PE, bool PW>
+int occupancy_blocks() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_close<CAP, PE, PW>, kBlock, 0) != hipSuccess || nb < 1)
+        nb = 1;
+    return nb;
+}
+
+template <int CAP, bool PE, bool PW>
+void launch_close(const CloseArgs &a, int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_close<CAP, PE, PW>), dim3(nblocks), dim3(kBlock), 0, s, a);
+    HTRI_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- LUT
+
+namespace {
+struct LutBuilder {
+    uint8_t lut[128];
+    LutBuilder() {
+        // regions: bit 0 a (i only), 1 b (j only), 2 c (k only), 3 d (i&j),
+        // 4 e (j&k), 5 f (k&i), 6 g (i&j&k)
+        const int single[3] = {0, 1, 2};
+        auto pair = [](int x, int y) {
+            int lo = x < y ? x : y, hi = x < y ? y : x;
+            if (lo == 0 && hi == 1) return 3;
+            if (lo == 1 && hi == 2) return 4;
+            return 5;
+        };
+        for (int msk = 0; msk < 128; msk++) {
+            auto on = [&](int bit) { return (msk >> bit) & 1; };
+            lut[msk] = 0;
+            if (!((on(3) || on(6)) && (on(4) || on(6)) && (on(5) || on(6)))) continue;
+            // set of non-empty regions inside hyperedge x
+            auto regions_of = [&](int x) {
+                int s = 0;
+                for (int b = 0; b < 7; b++) {
+                    bool in = (b == single[x]) || b == 6 || (b >= 3 && b <= 5 &&
+                              ((b == 3 && (x == 0 || x == 1)) || (b == 4 && (x == 1 || x == 2)) ||
+                               (b == 5 && (x == 0 || x == 2))));
+                    if (in && on(b)) s |= 1 << b;
+                }
+                return s;
+            };
+            int R[3] = {regions_of(0), regions_of(1), regions_of(2)};
+            if (R[0] == R[1] || R[1] == R[2] || R[0] == R[2]) continue;  // equal hyperedges
+            auto sub = [&](int x, int y) { return (R[x] & ~R[y]) == 0; };
+            bool C[3][3] = {};
+            int nc = 0;
+            for (int x = 0; x < 3; x++)
+                for (int y = x + 1; y < 3; y++) {
+                    C[x][y] = C[y][x] = sub(x, y) || sub(y, x);
+                    nc += C[x][y];
+                }
+            int p = 0;
+            if (nc == 3) {
+                p = 1;
+            } else if (nc == 2) {
+                int x = 0;
+                for (int c = 0; c < 3; c++)
+                    if (C[c][(c + 1) % 3] && C[c][(c + 2) % 3]) x = c;
+                int y = (x + 1) % 3, z = (x + 2) % 3;
+                if (sub(x, y)) p = on(pair(y, z)) ? 3 : 2;   // x inside both
+                else p = on(single[x]) ? 5 : 4;               // x contains both
+            } else if (nc == 1) {
+                int L = 0, S = 0, X = 0;
+                for (int x = 0; x < 3; x++)
+                    for (int y = 0; y < 3; y++)
+                        if (x != y && C[x][y] && sub(y, x)) { L = x; S = y; X = 3 - x - y; }
+                if (!on(pair(L, X))) p = 6;       // X meets L only inside S
+                else if (!on(single[L])) p = 7;   // L has no private vertex
+                else p = 8;
+            } else {
+                int s = on(0) + on(1) + on(2), q = on(3) + on(4) + on(5);
+                if (!on(6)) p = 17 + s;
+                else if (q == 0) p = 9;
+                else if (q == 1) p = 10;
+                else if (q == 2) p = (s == 2) ? 11 : 12;
+                else p = 13 + s;
+            }
+            lut[msk] = (uint8_t)p;
+        }
+    }
+};
+}  // namespace
+
+const uint8_t *pattern_lut() {
+    static LutBuilder b;
+    return b.lut;
+}
+
+// ---------------------------------------------------------------- driver
+
+constexpr int kCap = 512;
+
+void count_patterns(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev, uint32_t *cw_dev) {
+    hipStream_t s = g.stream;
+    Allocator &A = g.al;
+    const int64_t m = g.m;
+    hipEvent_t e0, e1, e2, e3;
+    HTRI_HIP(hipEventCreate(&e0));
+    HTRI_HIP(hipEventCreate(&e1));
+    HTRI_HIP(hipEventCreate(&e2));
+    HTRI_HIP(hipEventCreate(&e3));
+    HTRI_HIP(hipEventRecord(e0, s));
+
+    // schedule
+    DBuf<int64_t> icnt(A, m + 1);
+    if (m > 0) {
+        hipLaunchKernelGGL(k_item_counts<kCap>, dim3(grid_for(m, 256)), dim3(256), 0, s, g.fptr.p, m, icnt.p);
+        HTRI_LAUNCH_CHECK();
+    }
+    scan_exclusive_i64(A, icnt.p, icnt.p, m, icnt.p + m, s);
+    int64_t nitems = 0;
+    HTRI_HIP(hipMemcpyAsync(&nitems, icnt.p + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HTRI_HIP(hipStreamSynchronize(s));
+    if (nitems >= (int64_t)UINT32_MAX) fail(HTRI_E_UNSUPPORTED, "too many work items");
+    DBuf<Item> items(A, nitems);
+    if (m > 0) {
+        hipLaunchKernelGGL(k_item_fill<kCap>, dim3(grid_for(m, 256)), dim3(256), 0, s, g.fptr.p, m, icnt.p,
+                           items.p);
+        HTRI_LAUNCH_CHECK();
+    }
+    DBuf<uint8_t> lut(A, 128);
+    HTRI_HIP(hipMemcpyAsync(lut.p, pattern_lut(), 128, hipMemcpyHostToDevice, s));
+    DBuf<unsigned int> queue(A, 1);
+    fill_u32(queue.p, 1, 0, s);
+
+    const bool pe = t_dev != nullptr;
+    const bool pw = cw_dev != nullptr;
+    DBuf<uint32_t> cwjm, cwkm;
+    if (pe) {
+        cwjm.alloc(A, g.nw);
+        cwkm.alloc(A, g.nw);
+        fill_u32(cwjm.p, g.nw, 0, s);
+        fill_u32(cwkm.p, g.nw, 0, s);
+    }
+    if (pw) fill_u32(cw_dev, g.nw, 0, s);
+
+    int per_cu = pe ? (pw ? occupancy_blocks<kCap, true, true>() : occupancy_blocks<kCap, true, false>())
+                    : (pw ? occupancy_blocks<kCap, false, true>() : occupancy_blocks<kCap, false, false>());
+    int nblocks = device_cu_count() * per_cu;
+    if ((int64_t)nblocks > nitems) nblocks = (int)std::max<int64_t>(nitems, 1);
+    DBuf<unsigned long long> partials(A, (size_t)nblocks * 22);
+    HTRI_HIP(hipEventRecord(e1, s));
+
+    CloseArgs a;
+    a.items = items.p;
+    a.nitems = nitems;
+    a.queue = queue.p;
+    a.fptr = g.fptr.p;
+    a.fadj = g.fadj.p;
+    a.mptr = g.mptr.p;
+    a.fmask = g.fmask.p;
+    a.esize = g.esize.p;
+    a.eptr = g.eptr.p;
+    a.emem = g.emem.p;
+    a.wbits = g.wbits;
+    a.emask = mask;
+    a.lut = lut.p;
+    a.cwj = cw_dev;
+    a.cwjm = cwjm.p;
+    a.cwkm = cwkm.p;
+    a.partials = partials.p;
+    if (pe && pw) launch_close<kCap, true, true>(a, nblocks, s);
+    else if (pe) launch_close<kCap, true, false>(a, nblocks, s);
+    else if (pw) launch_close<kCap, false, true>(a, nblocks, s);
+    else launch_close<kCap, false, false>(a, nblocks, s);
+    HTRI_HIP(hipEventRecord(e2, s));
+
+    DBuf<long long> dcounts(A, 23);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(64), 0, s, partials.p, nblocks, dcounts.p);
+    HTRI_LAUNCH_CHECK();
+    fill_u64((uint64_t *)(dcounts.p + 22), 1, 0, s);
+    if (g.nw > 0) {
+        hipLaunchKernelGGL(k_stream_size, dim3(grid_for(g.nw, 256, 2048)), dim3(256), 0, s, g.fptr.p, g.fadj.p,
+                           g.nw, g.wbits, (unsigned long long *)(dcounts.p + 22));
+        HTRI_LAUNCH_CHECK();
+    }
+    if (pe) {
+        DBuf<unsigned long long> t(A, m);
+        fill_u64((uint64_t *)t.p, m, 0, s);
+        if (m > 0) {
+            hipLaunchKernelGGL(k_edge_counts, dim3(grid_for(m, 256)), dim3(256), 0, s, g.fptr.p, g.fadj.p, m,
+                               g.wbits, cwjm.p, cwkm.p, t.p);
+            HTRI_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_rank_to_norm_u64, dim3(grid_for(m, 256)), dim3(256), 0, s, t.p,
+                               g.norm_of_rank.p, m, (int64_t *)t_dev);
+            HTRI_LAUNCH_CHECK();
+        }
+    }
+    HTRI_HIP(hipEventRecord(e3, s));
+    int64_t hc[23];
+    HTRI_HIP(hipMemcpyAsync(hc, dcounts.p, sizeof(int64_t) * 23, hipMemcpyDeviceToHost, s));
+    HTRI_HIP(hipStreamSynchronize(s));
+    std::memcpy(counts, hc, sizeof(int64_t) * 21);
+    int64_t mask_words_total = 0;
+    HTRI_HIP(hipMemcpy(&mask_words_total, g.mptr.p + m, sizeof(int64_t), hipMemcpyDeviceToHost));
+    g.cstats[0] = hc[22];
+    g.cstats[1] = hc[21];
+    g.cstats[2] = nitems;
+    g.cstats[3] = mask_words_total;
+    g.cstats[4] = nblocks;
+    HTRI_HIP(hipEventElapsedTime(&g.tm.schedule_ms, e0, e1));
+    HTRI_HIP(hipEventElapsedTime(&g.tm.closure_ms, e1, e2));
+    HTRI_HIP(hipEventElapsedTime(&g.tm.reduce_ms, e2, e3));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+    (void)hipEventDestroy(e3);
+}
+
+}  // namespace htri

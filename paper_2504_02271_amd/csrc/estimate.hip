@@ -1,0 +1,154 @@
+// Hyperwedge-sampling estimators behind htri_estimate: the uniform estimator
+// of Algorithm 6 (sigma = 1) and importance sampling from a learned
+// proposal, optionally over a uniform candidate pool.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace htri {
+namespace {
+
+// CDF of the mixed proposal over the pool, from the inclusive scan of the
+// scores: cdf_u = (1 - lambda) * raw_u / raw_total + lambda * (u + 1) / P
+__global__ void k_mix_cdf(double *cdf, int64_t P, double lambda) {
+    const double tot = cdf[P - 1];
+    const double a = tot > 0 ? (1.0 - lambda) / tot : 0.0;
+    const double b = tot > 0 ? lambda / (double)P : 1.0 / (double)P;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < P; u += (int64_t)gridDim.x * blockDim.x)
+        cdf[u] = a * cdf[u] + b * (double)(u + 1);
+}
+
+}  // namespace
+}  // namespace htri
+
+using namespace htri;
+
+namespace {
+template <typename F>
+htri_status run_g(htri_graph *h, F &&fn) {
+    try {
+        fn();
+        return HTRI_OK;
+    } catch (const htri::Error &e) {
+        h->g.err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        h->g.err = "host allocation failed";
+        return HTRI_E_OOM;
+    }
+}
+}  // namespace
+
+extern "C" {
+
+htri_status htri_estimate(htri_graph *h, const htri_sample_params *p, double est[21], double stderr_[21],
+                          double *time_ms) {
+    if (!h || !p || !est) return HTRI_E_INVALID;
+    if (!h->g.have_wedges) {
+        h->g.err = "htri_build_wedges has not run";
+        return HTRI_E_STATE;
+    }
+    if (p->proposal != 0 && p->proposal != 1) {
+        h->g.err = "proposal must be 0 (uniform) or 1 (learned)";
+        return HTRI_E_INVALID;
+    }
+    if (p->proposal == 1 && !p->model) {
+        h->g.err = "the learned proposal needs a model";
+        return HTRI_E_INVALID;
+    }
+    if (p->defensive_mix < 0 || p->defensive_mix > 1 || !(p->budget_fraction >= 0)) {
+        h->g.err = "defensive_mix must lie in [0, 1] and budget_fraction >= 0";
+        return HTRI_E_INVALID;
+    }
+    return run_g(h, [&] {
+        Graph &g = h->g;
+        hipStream_t s = g.stream;
+        const int64_t nw = g.nw;
+        double e[21] = {0}, se[21] = {0};
+        if (nw == 0) {
+            std::memcpy(est, e, sizeof(e));
+            if (stderr_) std::memcpy(stderr_, se, sizeof(se));
+            if (time_ms) *time_ms = 0;
+            return;
+        }
+        int64_t n = p->num_samples > 0 ? p->num_samples : (int64_t)std::llround(p->budget_fraction * (double)nw);
+        if (n < 1) n = 1;
+        hipEvent_t e0, e1;
+        HTRI_HIP(hipEventCreate(&e0));
+        HTRI_HIP(hipEventCreate(&e1));
+        HTRI_HIP(hipEventRecord(e0, s));
+        long long c[21];
+        double y[21], y2[21];
+        if (p->proposal == 0) {
+            sample_sums(g, 1, n, p->seed, nullptr, nullptr, 0, (double)nw, c, y, y2);
+            HTRI_HIP(hipEventRecord(e1, s));
+            for (int q = 0; q < 21; q++) e[q] = (double)c[q] * (double)nw / (double)n;
+        } else {
+            int64_t P = nw;
+            DBuf<int64_t> pool;
+            if (p->pool_factor > 0) {
+                P = (int64_t)std::llround(p->pool_factor * (double)n);
+                P = std::max<int64_t>(P, 1);
+                pool.alloc(g.al, P);
+                draw_pool(g, p->seed, P, pool.p);
+            }
+            DBuf<double> score(g.al, P), cdf(g.al, P);
+            score_wedges(g, p->model, pool.p, P, score.p);
+            scan_inclusive_f64(g.al, score.p, cdf.p, P, s);
+            hipLaunchKernelGGL(k_mix_cdf, dim3(grid_for(P, 256, 8192)), dim3(256), 0, s, cdf.p, P, p->defensive_mix);
+            HTRI_LAUNCH_CHECK();
+            sample_sums(g, 2, n, p->seed, pool.p, cdf.p, P, (double)nw / (double)P, c, y, y2);
+            HTRI_HIP(hipEventRecord(e1, s));
+            for (int q = 0; q < 21; q++) e[q] = y[q] / (double)n;
+        }
+        HTRI_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        HTRI_HIP(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        for (int q = 0; q < 21; q++) {
+            const double var = (y2[q] - (double)n * e[q] * e[q]) / ((double)n * (double)std::max<int64_t>(n - 1, 1));
+            se[q] = std::sqrt(std::max(var, 0.0));
+        }
+        std::memcpy(est, e, sizeof(e));
+        if (stderr_) std::memcpy(stderr_, se, sizeof(se));
+        if (time_ms) *time_ms = ms;
+    });
+}
+
+htri_status htri_close_wedges(htri_graph *h, const int64_t *wedge_idx, int64_t n, int64_t *out) {
+    if (!h || n < 0 || (n > 0 && (!wedge_idx || !out))) return HTRI_E_INVALID;
+    if (!h->g.have_wedges) {
+        h->g.err = "htri_build_wedges has not run";
+        return HTRI_E_STATE;
+    }
+    for (int64_t t = 0; t < n; t++)
+        if (wedge_idx[t] < 0 || wedge_idx[t] >= h->g.nw) {
+            h->g.err = "wedge index out of range";
+            return HTRI_E_INVALID;
+        }
+    return run_g(h, [&] {
+        Graph &g = h->g;
+        if (n == 0) return;
+        DBuf<int64_t> idx(g.al, n), o(g.al, n * 21);
+        HTRI_HIP(hipMemcpyAsync(idx.p, wedge_idx, sizeof(int64_t) * n, hipMemcpyHostToDevice, g.stream));
+        close_wedge_list_counts(g, idx.p, n, o.p);
+        HTRI_HIP(hipMemcpyAsync(out, o.p, sizeof(int64_t) * n * 21, hipMemcpyDeviceToHost, g.stream));
+        HTRI_HIP(hipStreamSynchronize(g.stream));
+    });
+}
+
+htri_status htri_wedge_features(htri_graph *h, float *dev_features) {
+    if (!h || !dev_features) return HTRI_E_INVALID;
+    if (!h->g.have_wedges) {
+        h->g.err = "htri_build_wedges has not run";
+        return HTRI_E_STATE;
+    }
+    return run_g(h, [&] {
+        wedge_features_all(h->g, dev_features);
+        HTRI_HIP(hipStreamSynchronize(h->g.stream));
+    });
+}
+
+}  // extern "C"

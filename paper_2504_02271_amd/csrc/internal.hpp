@@ -1,0 +1,212 @@
+// Internal declarations of the htri HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "htri.h"
+
+namespace htri {
+
+constexpr int kWave = 64;
+
+// Status carried through the host code; converted to htri_status at the ABI.
+struct Error {
+    htri_status code;
+    std::string msg;
+};
+
+#define HTRI_HIP(expr)                                                                         \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            throw ::htri::Error{HTRI_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define HTRI_LAUNCH_CHECK() HTRI_HIP(hipGetLastError())
+
+inline void fail(htri_status code, const std::string &msg) { throw Error{code, msg}; }
+
+// Device memory through the caller's allocator (or hipMallocAsync/hipMalloc).
+struct Allocator {
+    htri_allocator user{};
+    bool has_user = false;
+    hipStream_t stream = nullptr;
+
+    void *alloc(size_t bytes) {
+        if (bytes == 0) bytes = 256;
+        void *p = nullptr;
+        if (has_user) {
+            p = user.alloc(bytes, (void *)stream, user.ctx);
+            if (!p) fail(HTRI_E_OOM, "allocator returned NULL for " + std::to_string(bytes) + " bytes");
+        } else {
+            hipError_t e = hipMalloc(&p, bytes);
+            if (e != hipSuccess || !p) {
+                (void)hipGetLastError();
+                fail(HTRI_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+            }
+        }
+        return p;
+    }
+    void release(void *p) {
+        if (!p) return;
+        if (has_user)
+            user.free(p, (void *)stream, user.ctx);
+        else
+            (void)hipFree(p);
+    }
+};
+
+// A device buffer owned by its scope.
+template <typename T>
+struct DBuf {
+    Allocator *a = nullptr;
+    T *p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    DBuf(Allocator &al, size_t count) : a(&al), n(count) { p = (T *)al.alloc(sizeof(T) * (count ? count : 1)); }
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : a(o.a), p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DBuf &operator=(DBuf &&o) noexcept {
+        if (this != &o) { reset(); a = o.a; p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DBuf() { reset(); }
+    void reset() {
+        if (p && a) a->release(p);
+        p = nullptr;
+        n = 0;
+    }
+    void alloc(Allocator &al, size_t count) {
+        reset();
+        a = &al;
+        n = count;
+        p = (T *)al.alloc(sizeof(T) * (count ? count : 1));
+    }
+    T *get() const { return p; }
+};
+
+inline int bits_for(uint64_t maxval) {  // bits to represent values 0..maxval
+    int b = 0;
+    while (b < 64 && (maxval >> b) != 0) b++;
+    return b == 0 ? 1 : b;
+}
+
+inline unsigned grid_for(int64_t n, int block, int64_t cap = 1 << 20) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+// ---------------------------------------------------------------- primitives
+// (prims.hip)
+// Exclusive prefix sum of n values; out may alias in.  total (may be NULL)
+// receives the sum on the device.
+void scan_exclusive_i64(Allocator &a, const int64_t *in, int64_t *out, int64_t n, int64_t *total,
+                        hipStream_t s);
+void scan_exclusive_u32(Allocator &a, const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total,
+                        hipStream_t s);
+// Stable LSD radix sort of 64-bit keys on bits [0, key_bits), optional
+// 32-bit payload, in place.
+void radix_sort_u64(Allocator &a, uint64_t *keys, uint32_t *vals, int64_t n, int key_bits,
+                    hipStream_t s);
+// Fill n values with v (kernel, safe inside graph capture).
+void fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+void fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
+int device_cu_count();
+
+// ---------------------------------------------------------------- graph state
+
+struct Timings {
+    float wedges_ms = 0, schedule_ms = 0, closure_ms = 0, reduce_ms = 0;
+};
+
+struct Graph {
+    Allocator al;
+    hipStream_t stream = nullptr;
+    uint32_t flags = 0;
+    std::string err;
+
+    int64_t m = 0;          // hyperedges after dedupe
+    int64_t removed = 0;
+    int64_t nnz = 0;        // memberships after removing repeated ids
+    int32_t n = 0;          // vertices
+    int32_t max_size = 0;
+
+    // normalised-id CSR (input order of survivors)
+    DBuf<int64_t> eptr_n;
+    DBuf<int32_t> emem_n;
+    std::vector<int64_t> norm_to_input;  // host
+
+    // internal (prec-order) CSR: rank r holds normalised hyperedge norm_of_rank[r]
+    DBuf<int32_t> norm_of_rank;
+    DBuf<int32_t> rank_of_norm;
+    DBuf<int64_t> eptr;
+    DBuf<int32_t> emem;
+    DBuf<int32_t> esize;
+    DBuf<int32_t> edge_of_mem;  // membership index -> rank
+    DBuf<int64_t> vptr;         // E_v lists, ascending rank
+    DBuf<int32_t> vadj;
+    DBuf<int32_t> vpos;         // membership -> its position inside E_v
+
+    // step 1: forward adjacency N+(r), sorted by rank
+    bool have_wedges = false;
+    int64_t nw = 0;
+    int wbits = 0;              // low bits of a packed entry hold omega
+    int rbits = 0;
+    DBuf<int64_t> fptr;         // m+1
+    DBuf<uint32_t> fadj;        // packed (dst << wbits) | omega
+    DBuf<int64_t> mptr;         // m+1, offsets (in 32-bit words) of Omega masks
+    DBuf<uint32_t> fmask;
+    DBuf<uint32_t> indeg;       // earlier neighbours of each hyperedge
+    int64_t summary[6] = {0, 0, 0, 0, 0, 0};
+
+    Timings tm;
+    int64_t cstats[5] = {0, 0, 0, 0, 0};
+};
+
+// load.hip
+void graph_load(Graph &g, const int64_t *off, int64_t m_in, const int32_t *mem, int32_t n,
+                uint32_t flags);
+// wedges.hip
+void build_wedges(Graph &g);
+// closure.hip
+struct CountOut {
+    int64_t counts[21];
+};
+void count_patterns(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev /*m or null*/,
+                    uint32_t *cw_dev /*nw or null*/);
+// sample.hip: closure of explicit wedges (per-sample counts) and weighted
+// sums over uniform (mode 1) or pool (mode 2) draws
+void close_wedge_list_counts(Graph &g, const int64_t *dev_idx, int64_t n, int64_t *dev_out);
+void sample_sums(Graph &g, int mode, int64_t n, uint64_t seed, const int64_t *pool, const double *cdf,
+                 int64_t pool_n, double scale, long long c[21], double y[21], double y2[21]);
+void draw_pool(Graph &g, uint64_t seed, int64_t pool_n, int64_t *dev_pool);
+void scan_inclusive_f64(Allocator &a, const double *in, double *out, int64_t n, hipStream_t s);
+
+}  // namespace htri
+
+// ABI handles
+struct htri_graph {
+    htri::Graph g;
+};
+struct htri_model;
+
+namespace htri {
+
+// mlp.hip: proposal features and scores
+void wedge_features_all(Graph &g, float *dev_out);
+// predicted closure count of each listed wedge (null list: wedges 0..n-1)
+void score_wedges(Graph &g, const htri_model *model, const int64_t *dev_wedges, int64_t n, double *dev_score);
+
+// Pattern of each 7-bit region-emptiness mask (bit 0 a .. bit 6 g), built
+// on the host by region rules; 0 for masks that are not hyper-triangles.
+const uint8_t *pattern_lut();
+
+}  // namespace htri

@@ -1,0 +1,316 @@
+// Hyperwedge sampling (Algorithm 6 with sigma = 1; unbiased by Lemma 4.1)
+// and its importance-sampling form with a learned proposal.
+//
+// A drawn hyperwedge (r, j) is closed exactly like in the exact count: the
+// third hyperedges k after j that lie in N+(r) and N+(j).  One wave closes
+// one sample by a tile merge of the two sorted lists (64 entries of each per
+// step, membership found by a 6-step shuffle search inside the other tile);
+// per-pattern counts are aggregated across the wave and kept in the lane
+// whose index is the pattern.  Samples are assigned to waves round-robin so
+// that every floating-point sum has a fixed order.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.hpp"
+#include "philox.hpp"
+
+namespace htri {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kMaskWordsMax = 4;
+
+__host__ __device__ __forceinline__ int mask_words(int size) {
+    return size <= 32 * kMaskWordsMax ? (size + 31) / 32 : 0;
+}
+
+__device__ int triple_common_s(const int64_t *eptr, const int32_t *emem, int32_t r, int32_t j, int32_t k) {
+    int64_t a = eptr[r], ae = eptr[r + 1], b = eptr[j], be = eptr[j + 1], c = eptr[k], ce = eptr[k + 1];
+    int cnt = 0;
+    while (a < ae && b < be && c < ce) {
+        int32_t x = emem[a], y = emem[b], z = emem[c];
+        if (x == y && y == z) { cnt++; a++; b++; c++; continue; }
+        int32_t mx = x > y ? x : y;
+        mx = mx > z ? mx : z;
+        if (x < mx) a++;
+        if (y < mx) b++;
+        if (z < mx) c++;
+    }
+    return cnt;
+}
+
+__device__ __forceinline__ uint32_t region_mask_s(int si, int sj, int sk, int wij, int wik, int wjk, int g) {
+    int a = si - wij - wik + g, b = sj - wij - wjk + g, c = sk - wik - wjk + g;
+    int d = wij - g, e = wjk - g, f = wik - g;
+    return (uint32_t)(a > 0) | ((uint32_t)(b > 0) << 1) | ((uint32_t)(c > 0) << 2) | ((uint32_t)(d > 0) << 3) |
+           ((uint32_t)(e > 0) << 4) | ((uint32_t)(f > 0) << 5) | ((uint32_t)(g > 0) << 6);
+}
+
+struct SampleArgs {
+    const int64_t *fptr;
+    const uint32_t *fadj;
+    const int64_t *mptr;
+    const uint32_t *fmask;
+    const int32_t *esize;
+    const int64_t *eptr;
+    const int32_t *emem;
+    int64_t m;
+    int64_t nw;
+    int wbits;
+    const uint8_t *lut;
+    int64_t n;                  // samples
+    // mode 0: explicit wedge list, per-sample counts out
+    const int64_t *idx;
+    int64_t *out_counts;        // n x 21
+    // mode 1: uniform draws (Philox stream 0); mode 2: pool draws by CDF
+    uint64_t seed;
+    const int64_t *pool;        // pool index -> wedge
+    const double *cdf;          // inclusive CDF over the pool
+    int64_t pool_n;
+    double scale;               // multiplies every closure (mode 1: |wedges|; mode 2: |wedges|/pool)
+    // accumulation: per wave [21] x (int64 sum c, double sum y, double sum y^2)
+    long long *acc_c;
+    double *acc_y;
+    double *acc_y2;
+};
+
+// owner of wedge e: largest r with fptr[r] <= e
+__device__ __forceinline__ int64_t owner_of(const int64_t *fptr, int64_t m, int64_t e) {
+    int64_t lo = 0, hi = m;  // answer in [0, m-1]
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) >> 1;
+        if (fptr[mid] <= e) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Close wedge e (global index into the forward adjacency).  Returns, in lane
+// p (1..20), the number of closing third hyperedges of pattern p and, in lane
+// 0, their total; other lanes return 0.
+__device__ long long wave_close(const SampleArgs &A, const uint8_t *lut, int64_t e) {
+    const int lane = __lane_id();
+    const uint32_t wmask = (1u << A.wbits) - 1;
+    const int64_t r = owner_of(A.fptr, A.m, e);
+    const int64_t rb = A.fptr[r];
+    const int64_t pos = e - rb;
+    const uint32_t jent = A.fadj[e];
+    const uint32_t j = jent >> A.wbits;
+    const int wrj = (int)(jent & wmask);
+    const int si = A.esize[r], sj = A.esize[j];
+    const int W = mask_words(si);
+    const int64_t mbase = A.mptr[r];
+    uint32_t mj[kMaskWordsMax];
+#pragma unroll
+    for (int w = 0; w < kMaskWordsMax; w++) mj[w] = w < W ? A.fmask[mbase + pos * W + w] : 0u;
+
+    int64_t a0 = e + 1, a1 = A.fptr[r + 1];         // N+(r) after j
+    int64_t b0 = A.fptr[j], b1 = A.fptr[j + 1];     // N+(j)
+    long long cnt = 0;
+    while (a0 < a1 && b0 < b1) {
+        const int64_t ia = a0 + lane, ib = b0 + lane;
+        const bool va = ia < a1, vb = ib < b1;
+        const uint32_t ae = va ? A.fadj[ia] : 0u;
+        const uint32_t be = vb ? A.fadj[ib] : 0u;
+        const uint32_t ak = va ? (ae >> A.wbits) : 0xFFFFFFFFu;
+        const uint32_t bk = vb ? (be >> A.wbits) : 0xFFFFFFFFu;
+        // position of ak among the b tile: number of b keys < ak
+        int p = 0;
+#pragma unroll
+        for (int s = 32; s >= 1; s >>= 1) {
+            uint32_t v = __shfl(bk, p + s - 1, kWave);
+            if (v < ak) p += s;
+        }
+        const int pc = p < kWave ? p : kWave - 1;
+        const uint32_t bk_at = __shfl(bk, pc, kWave);
+        const uint32_t be_at = __shfl(be, pc, kWave);
+        const bool hit = va && p < kWave && bk_at == ak;
+        int pat = 0;
+        if (hit) {
+            const uint32_t k = ak;
+            const int wrk = (int)(ae & wmask);
+            const int wjk = (int)(be_at & wmask);
+            const int sk = A.esize[k];
+            int g;
+            if (W > 0) {
+                const int64_t posk = ia - rb;
+                g = 0;
+#pragma unroll
+                for (int w = 0; w < kMaskWordsMax; w++)
+                    if (w < W) g += __popc(mj[w] & A.fmask[mbase + posk * W + w]);
+            } else {
+                g = triple_common_s(A.eptr, A.emem, (int32_t)r, (int32_t)j, (int32_t)k);
+            }
+            pat = lut[region_mask_s(si, sj, sk, wrj, wrk, wjk, g)];
+        }
+        uint64_t pend = __ballot(hit);
+        if (lane == 0) cnt += __popcll(pend);
+        while (pend) {
+            const int src = __ffsll((unsigned long long)pend) - 1;
+            const int p0 = __shfl(pat, src, kWave);
+            const uint64_t mm = __ballot(hit && pat == p0);
+            if (lane == p0) cnt += __popcll(mm);
+            pend &= ~mm;
+        }
+        // advance the tile whose largest key is smaller (both if equal)
+        const int la = (int)((a1 - a0) < kWave ? (a1 - a0) : kWave) - 1;
+        const int lb = (int)((b1 - b0) < kWave ? (b1 - b0) : kWave) - 1;
+        const uint32_t amax = __shfl(ak, la, kWave);
+        const uint32_t bmax = __shfl(bk, lb, kWave);
+        if (amax <= bmax) a0 += kWave;
+        if (bmax <= amax) b0 += kWave;
+    }
+    return cnt;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_sample_close(SampleArgs A) {
+    __shared__ uint8_t lut[128];
+    if (threadIdx.x < 128) lut[threadIdx.x] = A.lut[threadIdx.x];
+    __syncthreads();
+    const int lane = __lane_id();
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    long long sc = 0;
+    double sy = 0, sy2 = 0;
+    for (int64_t t = wave; t < A.n; t += nwaves) {
+        int64_t e;
+        double wgt = A.scale;
+        if (MODE == 0) {
+            e = A.idx[t];
+        } else if (MODE == 1) {
+            e = (int64_t)philox_index(A.seed, 0u, (uint64_t)t, (uint64_t)A.nw);
+        } else {
+            // inverse CDF over the pool: first u with cdf[u] > U * total
+            const double total = A.cdf[A.pool_n - 1];
+            const double U = philox_unit(A.seed, 2u, (uint64_t)t) * total;
+            int64_t lo = 0, hi = A.pool_n - 1;
+            while (lo < hi) {
+                int64_t mid = (lo + hi) >> 1;
+                if (A.cdf[mid] > U) hi = mid; else lo = mid + 1;
+            }
+            const double q = (A.cdf[lo] - (lo > 0 ? A.cdf[lo - 1] : 0.0)) / total;
+            e = A.pool ? A.pool[lo] : lo;
+            wgt = A.scale / q;
+        }
+        const long long c = wave_close(A, lut, e);
+        if (MODE == 0) {
+            if (lane < 21) A.out_counts[t * 21 + lane] = c;
+        } else {
+            sc += c;
+            const double y = (double)c * wgt;
+            sy += y;
+            sy2 += y * y;
+        }
+    }
+    if (MODE != 0 && lane < 21) {
+        A.acc_c[wave * 21 + lane] = sc;
+        A.acc_y[wave * 21 + lane] = sy;
+        A.acc_y2[wave * 21 + lane] = sy2;
+    }
+}
+
+// fixed-order reduction of the per-wave accumulators
+__global__ void k_sample_reduce(const long long *acc_c, const double *acc_y, const double *acc_y2, int64_t nwaves,
+                                long long *c, double *y, double *y2) {
+    const int p = threadIdx.x;
+    if (p >= 21) return;
+    long long s = 0;
+    double a = 0, b = 0;
+    for (int64_t w = 0; w < nwaves; w++) {
+        s += acc_c[w * 21 + p];
+        a += acc_y[w * 21 + p];
+        b += acc_y2[w * 21 + p];
+    }
+    c[p] = s;
+    y[p] = a;
+    y2[p] = b;
+}
+
+__global__ void k_pool_draw(uint64_t seed, int64_t pool_n, int64_t nw, int64_t *pool) {
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < pool_n;
+         u += (int64_t)gridDim.x * blockDim.x)
+        pool[u] = (int64_t)philox_index(seed, 1u, (uint64_t)u, (uint64_t)nw);
+}
+
+int sample_grid() { return device_cu_count() * 8; }
+
+SampleArgs base_args(Graph &g, const uint8_t *lut) {
+    SampleArgs a{};
+    a.fptr = g.fptr.p;
+    a.fadj = g.fadj.p;
+    a.mptr = g.mptr.p;
+    a.fmask = g.fmask.p;
+    a.esize = g.esize.p;
+    a.eptr = g.eptr.p;
+    a.emem = g.emem.p;
+    a.m = g.m;
+    a.nw = g.nw;
+    a.wbits = g.wbits;
+    a.lut = lut;
+    return a;
+}
+
+}  // namespace
+
+void close_wedge_list_counts(Graph &g, const int64_t *dev_idx, int64_t n, int64_t *dev_out) {
+    if (n <= 0) return;
+    hipStream_t s = g.stream;
+    DBuf<uint8_t> lut(g.al, 128);
+    HTRI_HIP(hipMemcpyAsync(lut.p, pattern_lut(), 128, hipMemcpyHostToDevice, s));
+    SampleArgs a = base_args(g, lut.p);
+    a.n = n;
+    a.idx = dev_idx;
+    a.out_counts = dev_out;
+    int grid = (int)std::min<int64_t>(sample_grid(), (n + kWavesPerBlock - 1) / kWavesPerBlock);
+    hipLaunchKernelGGL(k_sample_close<0>, dim3(std::max(grid, 1)), dim3(kBlock), 0, s, a);
+    HTRI_LAUNCH_CHECK();
+    HTRI_HIP(hipStreamSynchronize(s));
+}
+
+// Weighted closure sums over n draws.  mode 1: uniform (scale = |wedges|);
+// mode 2: from a pool by its CDF (scale = |wedges| / pool size).
+void sample_sums(Graph &g, int mode, int64_t n, uint64_t seed, const int64_t *pool, const double *cdf,
+                 int64_t pool_n, double scale, long long c[21], double y[21], double y2[21]) {
+    hipStream_t s = g.stream;
+    Allocator &A = g.al;
+    DBuf<uint8_t> lut(A, 128);
+    HTRI_HIP(hipMemcpyAsync(lut.p, pattern_lut(), 128, hipMemcpyHostToDevice, s));
+    const int grid = std::max(1, sample_grid());
+    const int64_t nwaves = (int64_t)grid * kWavesPerBlock;
+    DBuf<long long> ac(A, nwaves * 21);
+    DBuf<double> ay(A, nwaves * 21), ay2(A, nwaves * 21);
+    SampleArgs a = base_args(g, lut.p);
+    a.n = n;
+    a.seed = seed;
+    a.pool = pool;
+    a.cdf = cdf;
+    a.pool_n = pool_n;
+    a.scale = scale;
+    a.acc_c = ac.p;
+    a.acc_y = ay.p;
+    a.acc_y2 = ay2.p;
+    if (mode == 1)
+        hipLaunchKernelGGL(k_sample_close<1>, dim3(grid), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_sample_close<2>, dim3(grid), dim3(kBlock), 0, s, a);
+    HTRI_LAUNCH_CHECK();
+    DBuf<long long> dc(A, 21);
+    DBuf<double> dy(A, 21), dy2(A, 21);
+    hipLaunchKernelGGL(k_sample_reduce, dim3(1), dim3(64), 0, s, ac.p, ay.p, ay2.p, nwaves, dc.p, dy.p, dy2.p);
+    HTRI_LAUNCH_CHECK();
+    HTRI_HIP(hipMemcpyAsync(c, dc.p, sizeof(long long) * 21, hipMemcpyDeviceToHost, s));
+    HTRI_HIP(hipMemcpyAsync(y, dy.p, sizeof(double) * 21, hipMemcpyDeviceToHost, s));
+    HTRI_HIP(hipMemcpyAsync(y2, dy2.p, sizeof(double) * 21, hipMemcpyDeviceToHost, s));
+    HTRI_HIP(hipStreamSynchronize(s));
+}
+
+void draw_pool(Graph &g, uint64_t seed, int64_t pool_n, int64_t *dev_pool) {
+    if (pool_n <= 0) return;
+    hipLaunchKernelGGL(k_pool_draw, dim3(grid_for(pool_n, 256, 8192)), dim3(256), 0, g.stream, seed, pool_n, g.nw,
+                       dev_pool);
+    HTRI_LAUNCH_CHECK();
+}
+
+}  // namespace htri

@@ -1,0 +1,282 @@
+"""Python binding of libhtri (ctypes).  Argument marshalling only: every
+step of the computation runs in the HIP library.  PyTorch provides device
+memory (through the allocator callback) and the stream.
+
+Names follow the C ABI in include/htri.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhtri.so")
+
+HTRI_OK = 0
+HTRI_DEDUPE_EDGES = 1
+HTRI_INPUT_ON_DEVICE = 2
+HTRI_OUTPUT_ON_DEVICE = 4
+HTRI_ORDER_INPUT = 8
+HTRI_MODEL_NUM_PARAMS = 5313
+ALL_PATTERNS = 0x1FFFFE
+
+STATUS = {0: "HTRI_OK", -1: "HTRI_E_INVALID", -2: "HTRI_E_RANGE", -3: "HTRI_E_EMPTY_EDGE",
+          -4: "HTRI_E_DUPLICATE_EDGE", -5: "HTRI_E_OOM", -6: "HTRI_E_DEVICE", -7: "HTRI_E_OVERFLOW",
+          -8: "HTRI_E_STATE", -9: "HTRI_E_UNSUPPORTED"}
+
+
+class HtriError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str = ""):
+        super().__init__(f"{where}: {STATUS.get(code, code)}" + (f" ({msg})" if msg else ""))
+        self.code = code
+
+
+_P = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+class SampleParams(ctypes.Structure):
+    _fields_ = [("budget_fraction", ctypes.c_double), ("num_samples", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("proposal", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("model", ctypes.c_void_p), ("defensive_mix", ctypes.c_double),
+                ("pool_factor", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load libhtri.so; raise if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                          "(python -m paper_2504_02271_amd.build) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "htri_graph_load": ([_P, _i64, _P, _i32, _u32, _P, _P, ctypes.POINTER(_P)], ctypes.c_int),
+        "htri_graph_info": ([_P, _P], ctypes.c_int),
+        "htri_graph_edge_map": ([_P, _P], ctypes.c_int),
+        "htri_graph_csr": ([_P, _P, _P], ctypes.c_int),
+        "htri_build_wedges": ([_P, _P], ctypes.c_int),
+        "htri_get_wedges": ([_P, _P, _P, _P], ctypes.c_int),
+        "htri_count_patterns": ([_P, _u32, _P, _P, _P, _u32], ctypes.c_int),
+        "htri_last_timings": ([_P, _P], ctypes.c_int),
+        "htri_clear_wedges": ([_P], ctypes.c_int),
+        "htri_closure_stats": ([_P, _P], ctypes.c_int),
+        "htri_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "htri_last_error": ([_P], ctypes.c_char_p),
+        "htri_graph_free": ([_P], None),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _optional = {
+        "htri_estimate": ([_P, ctypes.POINTER(SampleParams), _P, _P, _P], ctypes.c_int),
+        "htri_close_wedges": ([_P, _P, _i64, _P], ctypes.c_int),
+        "htri_wedge_features": ([_P, _P], ctypes.c_int),
+        "htri_model_create": ([_u64, _P, ctypes.POINTER(_P)], ctypes.c_int),
+        "htri_model_free": ([_P], None),
+        "htri_model_get_params": ([_P, _P], ctypes.c_int),
+        "htri_model_set_params": ([_P, _P], ctypes.c_int),
+        "htri_model_forward": ([_P, _P, _i64, _P], ctypes.c_int),
+        "htri_model_loss_grad": ([_P, _P, _P, _i64, _P, _P], ctypes.c_int),
+        "htri_model_train": ([_P, _P, _P, _i64, _i32, _i32, ctypes.c_float, _u64, _P], ctypes.c_int),
+        "htri_batch_load": ([_i32, _P, _P, _P, _P, _u32, _P, ctypes.POINTER(_P)], ctypes.c_int),
+        "htri_batch_count": ([_P, _i32, _i32, _P, _P], ctypes.c_int),
+        "htri_batch_free": ([_P], None),
+    }
+    for name, (args, res) in _optional.items():
+        if hasattr(lib, name):
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = res
+    _lib = lib
+    return lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(rc: int, where: str, handle=None):
+    if rc != HTRI_OK:
+        msg = load_library().htri_last_error(handle)
+        raise HtriError(rc, where, msg.decode() if msg else "")
+
+
+# ---------------------------------------------------------------- torch glue
+
+class TorchMemory:
+    """Device memory from torch's caching allocator, handed to the library
+    through the htri_allocator callbacks; the stream is torch's current one."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.torch = torch
+        self.device = device
+
+        def _alloc(nbytes, stream, ctx):
+            try:
+                return self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device, stream)
+            except Exception:
+                return None
+
+        def _free(ptr, stream, ctx):
+            if ptr:
+                self.torch.cuda.caching_allocator_delete(ptr)
+
+        self._alloc_cb = ALLOC_FN(_alloc)
+        self._free_cb = FREE_FN(_free)
+        self.struct = Allocator(self._alloc_cb, self._free_cb, None)
+
+    def stream_handle(self) -> int:
+        return int(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+
+_default_mem: Optional[TorchMemory] = None
+
+
+def default_memory() -> TorchMemory:
+    global _default_mem
+    if _default_mem is None:
+        _default_mem = TorchMemory(0)
+    return _default_mem
+
+
+# ---------------------------------------------------------------- graph
+
+class Graph:
+    """A hypergraph resident on the GPU (htri_graph)."""
+
+    def __init__(self, handle, mem: Optional[TorchMemory]):
+        self._h = handle
+        self._mem = mem            # keeps the allocator callbacks alive
+        self._lib = load_library()
+        info = np.zeros(4, np.int64)
+        _check(self._lib.htri_graph_info(self._h, _ptr(info)), "htri_graph_info", self._h)
+        self.num_edges, self.removed, self.nnz, self.num_vertices = (int(x) for x in info)
+        self.summary: Optional[np.ndarray] = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.htri_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def edge_map(self) -> np.ndarray:
+        out = np.zeros(self.num_edges, np.int64)
+        _check(self._lib.htri_graph_edge_map(self._h, _ptr(out)), "htri_graph_edge_map", self._h)
+        return out
+
+    def csr(self) -> Tuple[np.ndarray, np.ndarray]:
+        off = np.zeros(self.num_edges + 1, np.int64)
+        mem = np.zeros(self.nnz, np.int32)
+        _check(self._lib.htri_graph_csr(self._h, _ptr(off), _ptr(mem)), "htri_graph_csr", self._h)
+        return off, mem
+
+    def build_wedges(self) -> np.ndarray:
+        s = np.zeros(6, np.int64)
+        _check(self._lib.htri_build_wedges(self._h, _ptr(s)), "htri_build_wedges", self._h)
+        self.summary = s
+        return s
+
+    @property
+    def num_wedges(self) -> int:
+        if self.summary is None:
+            self.build_wedges()
+        return int(self.summary[0])
+
+    def get_wedges(self) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+        nw = self.num_wedges
+        src = np.zeros(nw, np.int32)
+        dst = np.zeros(nw, np.int32)
+        om = np.zeros(nw, np.int32)
+        _check(self._lib.htri_get_wedges(self._h, _ptr(src), _ptr(dst), _ptr(om)), "htri_get_wedges", self._h)
+        return src, dst, om
+
+    def count_patterns(self, mask: int = 0, per_edge: bool = False, per_wedge: bool = False,
+                       device_out: bool = False):
+        """Returns (counts int64[21], per_edge or None, per_wedge or None).
+        With device_out the per-edge/per-wedge results are torch tensors on the GPU."""
+        counts = np.zeros(21, np.int64)
+        pe = pw = None
+        flags = 0
+        if device_out:
+            import torch
+            flags = HTRI_OUTPUT_ON_DEVICE
+            if per_edge:
+                pe = torch.empty(self.num_edges, dtype=torch.int64, device="cuda")
+            if per_wedge:
+                pw = torch.empty(self.num_wedges, dtype=torch.int32, device="cuda")
+            pe_p = pe.data_ptr() if pe is not None else None
+            pw_p = pw.data_ptr() if pw is not None else None
+        else:
+            if per_edge:
+                pe = np.zeros(self.num_edges, np.int64)
+            if per_wedge:
+                pw = np.zeros(self.num_wedges, np.int32)
+            pe_p = _ptr(pe)
+            pw_p = _ptr(pw)
+        _check(self._lib.htri_count_patterns(self._h, mask, _ptr(counts), pe_p, pw_p, flags),
+               "htri_count_patterns", self._h)
+        return counts, pe, pw
+
+    def clear_wedges(self) -> None:
+        _check(self._lib.htri_clear_wedges(self._h), "htri_clear_wedges", self._h)
+        self.summary = None
+
+    def closure_stats(self) -> np.ndarray:
+        """[S, probed entries, work items, Omega mask words, closure blocks]"""
+        out = np.zeros(5, np.int64)
+        _check(self._lib.htri_closure_stats(self._h, _ptr(out)), "htri_closure_stats", self._h)
+        return out
+
+    def last_timings(self) -> np.ndarray:
+        ms = np.zeros(4, np.float64)
+        _check(self._lib.htri_last_timings(self._h, _ptr(ms)), "htri_last_timings", self._h)
+        return ms
+
+
+def graph_load(offsets, members, num_vertices: int, flags: int = HTRI_DEDUPE_EDGES,
+               mem: Optional[TorchMemory] = None, use_torch: bool = True) -> Graph:
+    """Load a hypergraph (host numpy arrays, or torch CUDA tensors with
+    HTRI_INPUT_ON_DEVICE) and normalise it on the GPU."""
+    lib = load_library()
+    if use_torch and mem is None:
+        mem = default_memory()
+    stream = mem.stream_handle() if mem is not None else None
+    alloc = ctypes.byref(mem.struct) if mem is not None else None
+    h = ctypes.c_void_p()
+    if flags & HTRI_INPUT_ON_DEVICE:
+        off_p = ctypes.c_void_p(offsets.data_ptr())
+        mem_p = ctypes.c_void_p(members.data_ptr())
+        m = int(offsets.shape[0]) - 1
+    else:
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        members = np.ascontiguousarray(members, dtype=np.int32)
+        off_p, mem_p = _ptr(offsets), _ptr(members)
+        m = offsets.shape[0] - 1
+    rc = lib.htri_graph_load(off_p, m, mem_p, int(num_vertices), flags, alloc, stream, ctypes.byref(h))
+    _check(rc, "htri_graph_load", None)
+    return Graph(h, mem)

@@ -135,26 +135,23 @@ def generate(spec: GenSpec) -> HyperGraph:
     row = np.repeat(np.arange(m, dtype=np.int64), sizes)
     ranks = np.searchsorted(cdf, rng.random(nnz), side="right")
     np.minimum(ranks, nv - 1, out=ranks)
-    mem = perm[ranks]
+    key = row * nv + perm[ranks]
 
     # Without replacement inside a hyperedge: redraw repeated vertices until
-    # every hyperedge holds distinct vertices.
+    # every hyperedge holds distinct vertices.  Keys (hyperedge, vertex) are
+    # kept sorted, so members come out sorted within each hyperedge.
+    key.sort(kind="stable")
     for _ in range(10000):
-        order = np.lexsort((mem, row))
-        r_s = row[order]
-        m_s = mem[order]
-        dup = np.zeros(nnz, dtype=bool)
-        dup[1:] = (r_s[1:] == r_s[:-1]) & (m_s[1:] == m_s[:-1])
-        if not dup.any():
-            mem = m_s
-            row = r_s
+        dup = np.flatnonzero(key[1:] == key[:-1]) + 1
+        if dup.size == 0:
             break
-        idx = order[dup]
-        rr = np.searchsorted(cdf, rng.random(idx.shape[0]), side="right")
+        rr = np.searchsorted(cdf, rng.random(dup.size), side="right")
         np.minimum(rr, nv - 1, out=rr)
-        mem[idx] = perm[rr]
+        key[dup] = (key[dup] // nv) * nv + perm[rr]
+        key.sort(kind="stable")
     else:  # pragma: no cover - only with absurd parameters
         raise RuntimeError("could not draw distinct members")
+    mem = key % nv
 
     return HyperGraph(offsets=offsets, members=mem.astype(np.int32), num_vertices=nv,
                       name=spec.name)

@@ -1,0 +1,154 @@
+"""CPU-side checks: the HIP library loads and exports every declared entry
+point, the host-side references (Philox, estimators, network gradient) are
+pinned, and the input generators are deterministic."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+from oracle import mlp_ref, sampling
+from paper_2504_02271_amd import synth
+
+HEADER = os.path.join(ROOT, "include", "htri.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(htri_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    from paper_2504_02271_amd import htri
+    if not os.path.exists(htri.LIB_PATH):
+        pytest.skip("libhtri.so not built here (run __graft_entry__.build())")
+    lib = ctypes.CDLL(htri.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_2504_02271_amd import htri
+    monkeypatch.setattr(htri, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(htri, "_lib", None)
+    with pytest.raises(ImportError):
+        htri.load_library()
+
+
+def test_status_strings_without_gpu():
+    from paper_2504_02271_amd import htri
+    if not os.path.exists(htri.LIB_PATH):
+        pytest.skip("libhtri.so not built here")
+    lib = htri.load_library()
+    assert lib.htri_status_string(0) == b"ok"
+    assert lib.htri_status_string(-4) == b"duplicate hyperedge"
+    # argument checks run on the host and never touch the device
+    h = ctypes.c_void_p()
+    assert lib.htri_graph_load(None, 0, None, 0, 0, None, None, ctypes.byref(h)) == -1
+
+
+# ---------------------------------------------------------------- Philox
+
+def test_philox_known_answers():
+    rows = []
+    for line in open(os.path.join(ROOT, "tests", "golden", "philox4x32_10_kat.txt")):
+        line = line.split("#", 1)[0].strip()
+        if line:
+            c, k, o = (part.split() for part in line.split("|"))
+            rows.append(([int(x, 16) for x in c], [int(x, 16) for x in k], [int(x, 16) for x in o]))
+    assert len(rows) == 3
+    for c, k, o in rows:
+        got = [int(v) for v in sampling.philox4x32_10(c, k)]
+        assert got == o
+
+
+def test_uniform_indices_are_exact_mulhi():
+    u = sampling.draws_u64(42, 3, 2000)
+    for N in (1, 7, 10**6, 2**40 + 3):
+        idx = sampling.uniform_indices(42, 3, 2000, N)
+        assert all(int(a) * N >> 64 == int(b) for a, b in zip(u, idx))
+        assert idx.min() >= 0 and idx.max() < N
+
+
+def test_uniform_estimator_without_replacement_limit_is_exact():
+    """Closing every hyperwedge once and scaling by |wedges|/n recovers H."""
+    from oracle import core
+    g = synth.generate(synth.config("tiny"))
+    o = core.OracleGraph(g.offsets, g.members, g.num_vertices)
+    wi, wj, _ = o.wedges()
+    cl = o.wedge_closure(wi, wj)
+    est, _ = sampling.uniform_estimate(cl, wi.shape[0])
+    assert np.allclose(est, o.count().H, rtol=0, atol=1e-6)
+
+
+def test_uniform_estimator_is_unbiased_statistically():
+    """Lemma 4.1: mean of independent estimates within 4 standard errors."""
+    from oracle import core
+    g = synth.generate(synth.config("tiny"))
+    o = core.OracleGraph(g.offsets, g.members, g.num_vertices)
+    H = o.count().H
+    wi, wj, _ = o.wedges()
+    cl = o.wedge_closure(wi, wj)
+    R, n = 64, 2000
+    ests = []
+    for seed in range(R):
+        idx = sampling.uniform_indices(seed, 0, n, wi.shape[0])
+        ests.append(sampling.uniform_estimate(cl[idx], wi.shape[0])[0])
+    ests = np.array(ests)
+    mean = ests.mean(axis=0)
+    se = ests.std(axis=0, ddof=1) / np.sqrt(R)
+    for p in range(21):
+        if H[p] > 0 and se[p] > 0:
+            assert abs(mean[p] - H[p]) < 4 * se[p] + 1e-9, (p, mean[p], H[p], se[p])
+
+
+def test_relative_error_metric():
+    exact = np.zeros(21)
+    exact[[1, 9, 10]] = [4, 100, 10]
+    est = exact.copy()
+    est[9] = 110
+    m, rel = sampling.relative_error(est, exact)
+    assert abs(m - (0.1 / 3)) < 1e-12 and np.isnan(rel[1])
+
+
+# ---------------------------------------------------------------- network
+
+def test_network_gradient_matches_finite_differences():
+    rng = np.random.default_rng(0)
+    theta = rng.normal(scale=0.3, size=mlp_ref.NUM_PARAMS)
+    X = rng.normal(size=(40, 16))
+    y = rng.normal(size=40)
+    L, g = mlp_ref.loss_grad(theta, X, y)
+    assert abs(L - mlp_ref.loss(theta, X, y)) < 1e-12
+    idx = rng.choice(mlp_ref.NUM_PARAMS, size=80, replace=False).tolist() + [mlp_ref.NUM_PARAMS - 1]
+    fd = mlp_ref.finite_difference(theta, X, y, idx)
+    assert np.allclose(g[idx], fd, rtol=1e-5, atol=1e-7)
+    assert mlp_ref.NUM_PARAMS == 5313
+
+
+def test_network_layout_matches_the_header():
+    text = open(HEADER).read()
+    assert f"#define HTRI_MODEL_NUM_PARAMS {mlp_ref.NUM_PARAMS}" in text
+
+
+# ---------------------------------------------------------------- generators
+
+def test_generators_deterministic_and_shaped():
+    a = synth.generate(synth.config("coauth", 0.02))
+    b = synth.generate(synth.config("coauth", 0.02))
+    assert a.sha256() == b.sha256()
+    sizes = np.diff(a.offsets)
+    assert sizes.min() >= 2 and sizes.max() <= 25
+    for x in range(0, a.num_edges, 97):
+        e = a.edge(x)
+        assert (np.diff(e) > 0).all()
+    t = synth.generate(synth.config("tiny"))
+    assert t.num_edges == 2000 and np.diff(t.offsets).min() >= 2 and np.diff(t.offsets).max() <= 5
+    specs = synth.batch_specs(512)
+    es = np.array([s.num_edges for s in specs])
+    assert len(specs) == 512 and es.min() >= 1000 and es.max() <= 200000

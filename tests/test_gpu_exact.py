@@ -1,0 +1,213 @@
+"""GPU parity of the exact path (CSR build, hyperwedges, closure + classify +
+reduce) against the CPU oracle, element by element, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+from conftest import load_golden
+from oracle import core
+from paper_2504_02271_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def htri():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2504_02271_amd import htri as h
+    h.load_library()
+    return h
+
+
+def _orient(rank, a, b):
+    lo = np.where(rank[a] < rank[b], a, b)
+    hi = np.where(rank[a] < rank[b], b, a)
+    return lo, hi
+
+
+def check_exact(htri, g, flags=None, wedge_sample=None, nthreads=0, seed=0):
+    """Full parity on one hypergraph; returns (GPU graph, oracle graph, counts)."""
+    if flags is None:
+        flags = htri.HTRI_DEDUPE_EDGES
+    print(f"\n[check_exact] {g.name} m={g.num_edges} nnz={g.nnz} flags={flags}", flush=True)
+    G = htri.graph_load(g.offsets, g.members, g.num_vertices, flags=flags)
+    o = core.OracleGraph(g.offsets, g.members, g.num_vertices)
+    # a0: normalised CSR, byte for byte, and the id map
+    off, mem = G.csr()
+    ooff, omem, orig = o.csr()
+    assert G.num_edges == o.m and G.removed == o.removed
+    assert np.array_equal(off, ooff) and np.array_equal(mem, omem)
+    assert np.array_equal(G.edge_map(), orig)
+    # a1: hyperwedges with omega; summary
+    s = G.build_wedges()
+    assert np.array_equal(s, o.summary()), (s, o.summary())
+    src, dst, om = G.get_wedges()
+    wi, wj, wo = o.wedges()
+    lo, hi = np.minimum(src, dst), np.maximum(src, dst)
+    got = np.lexsort((hi, lo))
+    assert np.array_equal(lo[got], wi) and np.array_equal(hi[got], wj) and np.array_equal(om[got], wo)
+    # a2 + a3: per-pattern and per-hyperedge counts, per-wedge closure
+    counts, pe, pw = G.count_patterns(per_edge=True, per_wedge=True)
+    r = o.count(nthreads=nthreads)
+    assert np.array_equal(counts, r.H), (counts, r.H)
+    assert np.array_equal(pe, r.t)
+    assert int(pw.astype(np.int64).sum()) == int(counts[0])
+    if flags & htri.HTRI_ORDER_INPUT:
+        rank = np.arange(o.m, dtype=np.int64)
+    else:
+        rank = core.prec_rank(ooff, omem, g.num_vertices)
+    assert (rank[src] < rank[dst]).all()
+    idx = np.arange(src.shape[0])
+    if wedge_sample is not None and wedge_sample < idx.shape[0]:
+        rng = np.random.default_rng(seed)
+        idx = np.sort(rng.choice(idx.shape[0], size=wedge_sample, replace=False))
+    want = o.wedge_closure_ranked(rank, src[idx], dst[idx])[:, 0]
+    assert np.array_equal(pw[idx].astype(np.int64), want)
+    return G, o, counts
+
+
+def test_tiny_workload(htri):
+    check_exact(htri, synth.generate(synth.config("tiny")))
+
+
+def test_tiny_input_order(htri):
+    check_exact(htri, synth.generate(synth.config("tiny")),
+                flags=htri.HTRI_DEDUPE_EDGES | htri.HTRI_ORDER_INPUT)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_small_universes_every_pattern(htri, seed):
+    g = synth.random_small(seed, 50 + 5 * seed, 5 + 3 * seed, 1, 6)
+    check_exact(htri, g)
+
+
+def test_all_patterns_covered_together(htri):
+    tot = np.zeros(21, np.int64)
+    for seed in range(12):
+        g = synth.random_small(seed, 50 + 5 * seed, 5 + 3 * seed, 1, 6)
+        G = htri.graph_load(g.offsets, g.members, g.num_vertices)
+        G.build_wedges()
+        tot += G.count_patterns()[0]
+    assert (tot[1:] > 0).all(), tot
+
+
+def test_printed_examples(htri):
+    for name, want in (("fig6_coauthorship.txt", {10: 5, 12: 2}), ("fig7_email.txt", {5: 3})):
+        edges, _, _ = load_golden(name)
+        g = synth.from_lists(edges)
+        G, _, counts = check_exact(htri, g)
+        for p, c in want.items():
+            assert counts[p] == c
+
+
+def test_unsorted_members_with_repeats(htri):
+    g = synth.generate(synth.config("tiny"))
+    rng = np.random.default_rng(1)
+    edges = []
+    for x in range(g.num_edges):
+        e = list(g.edge(x))
+        if x % 3 == 0:
+            e = e + [e[0]]           # a repeated id counts once
+        rng.shuffle(e)
+        edges.append(e)
+    edges += [list(reversed(edges[5])), edges[7]]   # duplicate hyperedges
+    h = synth.from_lists(edges, g.num_vertices, "tiny-shuffled")
+    G, o, _ = check_exact(htri, h)
+    assert G.removed == 2
+
+
+def test_heavy_clique_multichunk_and_wide_edges(htri):
+    """Owners whose forward list spans several LDS chunks, partner pieces that
+    need the chunk's rank range, and hyperedges too wide for stored masks."""
+    rng = np.random.default_rng(7)
+    edges = []
+    for x in range(1500):                        # all share vertex 0
+        extra = rng.choice(np.arange(1, 300), size=int(rng.integers(1, 4)), replace=False)
+        edges.append([0] + sorted(extra.tolist()))
+    for x in range(400):                         # background over the same pool
+        edges.append(sorted(rng.choice(np.arange(1, 300), size=3, replace=False).tolist()))
+    edges.append(list(range(100, 400)))          # 300 vertices: no stored mask
+    edges.append(list(range(150, 290)))          # 140 vertices, inside the previous one
+    edges.append([0] + list(range(1, 200)))      # wide hyperedge with the hub
+    g = synth.from_lists(edges, 400, "clique")
+    G, o, counts = check_exact(htri, g, wedge_sample=20000)
+    assert counts[0] >= math.comb(1500, 3)
+
+
+def test_empty_and_wedgeless(htri):
+    g = synth.from_lists([], 5, "empty")
+    G = htri.graph_load(g.offsets, g.members, 5)
+    assert G.num_edges == 0
+    assert G.build_wedges().tolist() == [0, 0, 0, 0, 0, 0]
+    counts, pe, pw = G.count_patterns(per_edge=True, per_wedge=True)
+    assert (counts == 0).all() and pe.shape == (0,) and pw.shape == (0,)
+    g = synth.from_lists([[0, 1], [2, 3], [4]], 5, "disjoint")
+    G = htri.graph_load(g.offsets, g.members, 5)
+    assert G.build_wedges()[0] == 0
+    counts, pe, _ = G.count_patterns(per_edge=True)
+    assert (counts == 0).all() and (pe == 0).all()
+    g = synth.from_lists([[0, 1], [1, 2]], 3, "one-wedge")
+    check_exact(htri, g)
+
+
+def test_errors(htri):
+    g = synth.from_lists([[0, 1], [1, 0], [2]], 3)
+    with pytest.raises(htri.HtriError) as e:
+        htri.graph_load(g.offsets, g.members, 3, flags=0)
+    assert e.value.code == -4
+    g = synth.from_lists([[0, 1], [], [2]], 3)
+    with pytest.raises(htri.HtriError) as e:
+        htri.graph_load(g.offsets, g.members, 3)
+    assert e.value.code == -3
+    g = synth.from_lists([[0, 1], [5]], 3)
+    with pytest.raises(htri.HtriError) as e:
+        htri.graph_load(g.offsets, g.members, 3)
+    assert e.value.code == -2
+    bad = np.array([0, 2, 1], np.int64)
+    with pytest.raises(htri.HtriError) as e:
+        htri.graph_load(bad, np.zeros(2, np.int32), 3)
+    assert e.value.code == -1
+    g = synth.from_lists([[0, 1], [1, 2]], 3)
+    G = htri.graph_load(g.offsets, g.members, 3)
+    with pytest.raises(htri.HtriError) as e:
+        G.count_patterns()
+    assert e.value.code == -8
+
+
+def test_pattern_mask_for_per_edge_counts(htri):
+    g = synth.random_small(3, 120, 12, 1, 6)
+    G = htri.graph_load(g.offsets, g.members, g.num_vertices)
+    G.build_wedges()
+    o = core.OracleGraph(g.offsets, g.members, g.num_vertices)
+    for mask in ((1 << 9), (1 << 1) | (1 << 5) | (1 << 17), 0x1FFFFE & ~(1 << 9)):
+        counts, pe, _ = G.count_patterns(mask=mask, per_edge=True)
+        r = o.count(edge_mask=mask)
+        assert np.array_equal(counts, r.H)
+        assert np.array_equal(pe, r.t)
+
+
+def test_device_input_and_output(htri):
+    import torch
+    g = synth.generate(synth.config("tiny"))
+    off = torch.from_numpy(g.offsets).cuda()
+    mem = torch.from_numpy(g.members).cuda()
+    G = htri.graph_load(off, mem, g.num_vertices, flags=htri.HTRI_DEDUPE_EDGES | htri.HTRI_INPUT_ON_DEVICE)
+    G.build_wedges()
+    counts, pe, pw = G.count_patterns(per_edge=True, per_wedge=True, device_out=True)
+    o = core.OracleGraph(g.offsets, g.members, g.num_vertices)
+    r = o.count()
+    assert np.array_equal(counts, r.H)
+    assert np.array_equal(pe.cpu().numpy(), r.t)
+    assert int(pw.sum().item()) == int(r.H[0])
+
+
+def test_coauthorship_workload(htri):
+    """|V|=1e5, |E|=5e5, sizes TPL[2,25], Zipf(1.1) head: every count exact,
+    per-wedge closures on a sample, and bit-identical repeat runs."""
+    g = synth.generate(synth.config("coauth"))
+    G, o, counts = check_exact(htri, g, wedge_sample=5000)
+    c2, pe2, pw2 = G.count_patterns(per_edge=True, per_wedge=True)
+    c3, pe3, pw3 = G.count_patterns(per_edge=True, per_wedge=True)
+    assert np.array_equal(c2, c3) and np.array_equal(pe2, pe3) and np.array_equal(pw2, pw3)
