@@ -223,6 +223,47 @@ htri_status htri_model_train(htri_model *m, const float *dev_x, const float *dev
                              int32_t steps, int32_t batch, float lr, uint64_t seed,
                              double *final_loss);
 
+/* ---------------------------------------------------------------- batching */
+
+typedef struct htri_batch htri_batch;
+
+/* Closure schedule: chunk = entries of N+(r) held in LDS per work item (256
+ * or 512), partners = hyperwedges (r, j) per work item (128 or 256), order =
+ * 0 (work items in graph order) or 1 (graphs with the most hyperwedges
+ * started first). */
+typedef struct {
+    int32_t chunk;
+    int32_t partners;
+    int32_t order;
+} htri_schedule;
+
+/* Load `count` independent hypergraphs (host CSR arrays, one per graph, as
+ * in htri_graph_load), normalise them and build their hyperwedges.  flags:
+ * 0 or HTRI_DEDUPE_EDGES.  The batch owns a stream of its own (default
+ * priority) and device memory from hipMalloc.  Errors as htri_graph_load,
+ * the message (htri_batch_last_error / htri_last_error(NULL)) names the
+ * graph. */
+htri_status htri_batch_load(int32_t count, const int64_t *const *edge_offsets, const int64_t *num_edges,
+                            const int32_t *const *members, const int32_t *num_vertices, uint32_t flags,
+                            htri_batch **out);
+/* Hyperwedges of every graph, int64[count]. */
+htri_status htri_batch_info(const htri_batch *b, int64_t *wedges_per_graph);
+/* Exact count of every pattern of every graph in ONE persistent launch of the
+ * closure kernel (all graphs' work items in one queue), replayed from a
+ * captured HIP graph when use_graph != 0.  counts: int64[count][21] host
+ * array ([g][0] total).  time_ms: device time of the launch. */
+htri_status htri_batch_count(htri_batch *b, const htri_schedule *sched, int32_t use_graph, int64_t *counts,
+                             double *time_ms);
+/* Try every schedule (graph-replayed, best of `repeats` runs each) and
+ * return the fastest. */
+htri_status htri_batch_autotune(htri_batch *b, int32_t repeats, htri_schedule *best, double *best_ms);
+/* Baseline: the same counts with one closure launch per graph, issued back
+ * to back on the batch's stream; time_ms covers all launches. */
+htri_status htri_batch_count_per_graph(htri_batch *b, const htri_schedule *sched, int64_t *counts,
+                                       double *time_ms);
+const char *htri_batch_last_error(const htri_batch *b);
+void htri_batch_free(htri_batch *b); /* NULL-safe */
+
 /* ---------------------------------------------------------------- misc */
 
 const char *htri_status_string(htri_status s);

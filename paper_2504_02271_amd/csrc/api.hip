@@ -31,6 +31,13 @@ htri_status run(htri::Graph *g, F &&fn) {
 
 }  // namespace
 
+namespace htri {
+void set_load_error(const std::string &msg) {
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    g_load_err = msg;
+}
+}  // namespace htri
+
 extern "C" {
 
 const char *htri_status_string(htri_status s) {

@@ -25,13 +25,8 @@ namespace htri {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kJPiece = 256;            // partners per item (one thread each)
 constexpr int kMaskWordsMax = 4;
 constexpr uint64_t kEmpty = ~0ull;
-
-struct Item {
-    int32_t r, cb, ce, jb, je;
-};
 
 __host__ __device__ __forceinline__ int mask_words(int size) {
     return size <= 32 * kMaskWordsMax ? (size + 31) / 32 : 0;
@@ -75,53 +70,44 @@ __device__ __forceinline__ uint32_t region_mask(int si, int sj, int sk, int wij,
            ((uint32_t)(e > 0) << 4) | ((uint32_t)(f > 0) << 5) | ((uint32_t)(g > 0) << 6);
 }
 
-struct CloseArgs {
-    const Item *items;
-    int64_t nitems;
-    unsigned int *queue;            // item counter
-    const int64_t *fptr;
-    const uint32_t *fadj;
-    const int64_t *mptr;
-    const uint32_t *fmask;
-    const int32_t *esize;
-    const int64_t *eptr;
-    const int32_t *emem;
-    int wbits;
-    uint32_t emask;                 // patterns counted into per-edge counts
-    const uint8_t *lut;             // device copy of the 128-entry table
-    uint32_t *cwj;                  // per-wedge j-role count, all patterns (or null)
-    uint32_t *cwjm;                 // per-wedge j-role count, masked (or null)
-    uint32_t *cwkm;                 // per-wedge k-role count, masked (or null)
-    unsigned long long *partials;   // [gridDim.x][22]: patterns, then probes
-};
+// Add the per-lane pattern counters to counts[g] and clear them.
+__device__ __forceinline__ void flush_counts(uint32_t (*pcnt)[kBlock], unsigned long long *counts, int g, int tid) {
+    __syncthreads();
+    if (tid >= 1 && tid < 21) {
+        unsigned long long s = 0;
+        for (int l = 0; l < kBlock; l++) s += pcnt[tid][l];
+        if (s) atomicAdd(&counts[(int64_t)g * 21 + tid], s);
+    }
+    __syncthreads();
+    for (int p = 0; p < 21; p++) pcnt[p][tid] = 0;
+}
 
-template <int CAP, bool PER_EDGE, bool PER_WEDGE>
+template <int CAP, int JP, bool PER_EDGE, bool PER_WEDGE>
 __global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
+    static_assert(JP <= kBlock, "one thread per partner");
     constexpr int HMAX = 2 * CAP;
     __shared__ uint64_t tab[HMAX];
     __shared__ uint32_t ent_size[CAP];
     __shared__ uint32_t ent_mask[CAP * kMaskWordsMax];
     __shared__ uint32_t ent_ck[PER_EDGE ? CAP : 1];
-    __shared__ int64_t seg_pre[kJPiece + 1];
-    __shared__ int64_t seg_src[kJPiece];
-    __shared__ uint32_t seg_size[kJPiece];
-    __shared__ uint32_t seg_om[kJPiece];
-    __shared__ uint32_t seg_mask[kJPiece * kMaskWordsMax];
-    __shared__ uint32_t seg_cj[kJPiece];
-    __shared__ uint32_t seg_cjm[PER_EDGE ? kJPiece : 1];
+    __shared__ int64_t seg_pre[kBlock + 1];
+    __shared__ int64_t seg_src[JP];
+    __shared__ uint32_t seg_size[JP];
+    __shared__ uint32_t seg_om[JP];
+    __shared__ uint32_t seg_mask[JP * kMaskWordsMax];
+    __shared__ uint32_t seg_cj[PER_WEDGE ? JP : 1];
+    __shared__ uint32_t seg_cjm[PER_EDGE ? JP : 1];
     __shared__ uint32_t pcnt[21][kBlock];
-    __shared__ unsigned long long pacc[21];
     __shared__ uint8_t lut[128];
     __shared__ int64_t sh_item;
     __shared__ int64_t sh_scan[kBlock / kWave + 1];
 
     const int tid = threadIdx.x;
-    const uint32_t wmask = (1u << A.wbits) - 1;
     for (int p = 0; p < 21; p++) pcnt[p][tid] = 0;
-    if (tid < 21) pacc[tid] = 0;
     if (tid < 128) lut[tid] = A.lut[tid];
     uint64_t block_probes = 0;
     unsigned long long all_probes = 0;
+    int cur_g = -1;
 
     for (;;) {
         __syncthreads();
@@ -133,28 +119,35 @@ __global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
         const int64_t it = sh_item;
         if (it < 0) break;
         const Item item = A.items[it];
+        if (item.g != cur_g) {
+            if (cur_g >= 0) flush_counts(pcnt, A.counts, cur_g, tid);
+            cur_g = item.g;
+        }
+        const GraphDesc G = A.graphs[item.g];
+        const uint32_t wmask = (1u << G.wbits) - 1;
         const int32_t r = item.r;
-        const int64_t base = A.fptr[r];
-        const int32_t d = (int32_t)(A.fptr[r + 1] - base);
+        const int64_t base = G.fptr[r];
+        const int32_t d = (int32_t)(G.fptr[r + 1] - base);
         const bool single = item.cb == 0 && item.ce == d && item.jb == 0 && item.je == d - 1;
-        const int si = A.esize[r];
+        const int si = G.esize[r];
         const int W = mask_words(si);
-        const int64_t mbase = A.mptr[r];
+        const int64_t mbase = G.mptr[r];
         const int cl = item.ce - item.cb;
         int hbits = 6;
         while ((1 << hbits) < 2 * cl) hbits++;
         const int H = 1 << hbits;
-        const uint32_t lo = A.fadj[base + item.cb] >> A.wbits;
-        const uint32_t hi = A.fadj[base + item.ce - 1] >> A.wbits;
+        const uint32_t lo = G.fadj[base + item.cb] >> G.wbits;
+        const uint32_t hi = G.fadj[base + item.ce - 1] >> G.wbits;
 
         for (int s = tid; s < H; s += kBlock) tab[s] = kEmpty;
         __syncthreads();
         // stage the chunk
         for (int q = tid; q < cl; q += kBlock) {
-            uint32_t ent = A.fadj[base + item.cb + q];
-            uint32_t k = ent >> A.wbits;
-            ent_size[q] = (uint32_t)A.esize[k];
-            for (int w = 0; w < W; w++) ent_mask[q * kMaskWordsMax + w] = A.fmask[mbase + (int64_t)(item.cb + q) * W + w];
+            uint32_t ent = G.fadj[base + item.cb + q];
+            uint32_t k = ent >> G.wbits;
+            ent_size[q] = (uint32_t)G.esize[k];
+            for (int w = 0; w < W; w++)
+                ent_mask[q * kMaskWordsMax + w] = G.fmask[mbase + (int64_t)(item.cb + q) * W + w];
             if (PER_EDGE) ent_ck[q] = 0;
             uint64_t v = ((uint64_t)q << 32) | ent;
             uint32_t slot = hslot(k, hbits);
@@ -162,24 +155,24 @@ __global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
                              (unsigned long long)v) != kEmpty)
                 slot = (slot + 1) & (H - 1);
         }
-        // partner segments
+        // partner segments: N+(j) cut to the chunk's rank range
         const int nseg = item.je - item.jb;
         int64_t len = 0;
         if (tid < nseg) {
             const int pj = item.jb + tid;
-            const uint32_t jent = A.fadj[base + pj];
-            const uint32_t j = jent >> A.wbits;
-            int64_t a = A.fptr[j], b = A.fptr[j + 1];
+            const uint32_t jent = G.fadj[base + pj];
+            const uint32_t j = jent >> G.wbits;
+            int64_t a = G.fptr[j], b = G.fptr[j + 1];
             if (!single) {
-                a = lower_rank(A.fadj, a, b, lo, A.wbits);
-                b = lower_rank(A.fadj, a, b, hi + 1, A.wbits);
+                a = lower_rank(G.fadj, a, b, lo, G.wbits);
+                b = lower_rank(G.fadj, a, b, hi + 1, G.wbits);
             }
             len = b - a;
             seg_src[tid] = a;
-            seg_size[tid] = (uint32_t)A.esize[j];
+            seg_size[tid] = (uint32_t)G.esize[j];
             seg_om[tid] = jent & wmask;
-            for (int w = 0; w < W; w++) seg_mask[tid * kMaskWordsMax + w] = A.fmask[mbase + (int64_t)pj * W + w];
-            seg_cj[tid] = 0;
+            for (int w = 0; w < W; w++) seg_mask[tid * kMaskWordsMax + w] = G.fmask[mbase + (int64_t)pj * W + w];
+            if (PER_WEDGE) seg_cj[tid] = 0;
             if (PER_EDGE) seg_cjm[tid] = 0;
         }
         // exclusive scan of segment lengths
@@ -211,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
         block_probes += (uint64_t)total;
         all_probes += (unsigned long long)total;
 
-        // stream the partner lists
+        // stream the partner lists through the hash
         int q = -1;
         int sj = 0, wij = 0;
         uint32_t mj[kMaskWordsMax] = {0, 0, 0, 0};
@@ -225,7 +218,6 @@ __global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
                     if (PER_EDGE && cjm) atomicAdd(&seg_cjm[q], cjm);
                 }
                 cj = cjm = 0;
-                // upper bound of f in seg_pre[q+1 .. nseg]
                 int lo_s = q < 0 ? 0 : q + 1, hi_s = nseg;
                 while (lo_s < hi_s) {
                     int mid = (lo_s + hi_s) >> 1;
@@ -237,15 +229,15 @@ __global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
 #pragma unroll
                 for (int w = 0; w < kMaskWordsMax; w++) mj[w] = w < W ? seg_mask[q * kMaskWordsMax + w] : 0u;
                 src = seg_src[q] - seg_pre[q];
-                jrank = (int32_t)(A.fadj[base + item.jb + q] >> A.wbits);
+                jrank = (int32_t)(G.fadj[base + item.jb + q] >> G.wbits);
             }
-            const uint32_t ent = A.fadj[src + f];
-            const uint32_t k = ent >> A.wbits;
+            const uint32_t ent = G.fadj[src + f];
+            const uint32_t k = ent >> G.wbits;
             uint32_t slot = hslot(k, hbits);
             uint64_t v;
             for (;;) {
                 v = tab[slot];
-                if (v == kEmpty || ((uint32_t)v >> A.wbits) == k) break;
+                if (v == kEmpty || ((uint32_t)v >> G.wbits) == k) break;
                 slot = (slot + 1) & (H - 1);
             }
             if (v != kEmpty) {
@@ -260,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
                     for (int w = 0; w < kMaskWordsMax; w++)
                         if (w < W) g += __popc(mj[w] & ent_mask[pos * kMaskWordsMax + w]);
                 } else {
-                    g = triple_common(A.eptr, A.emem, r, jrank, (int32_t)k);
+                    g = triple_common(G.eptr, G.emem, r, jrank, (int32_t)k);
                 }
                 const uint32_t p = lut[region_mask(si, sj, sk, wij, wik, wjk, g)];
                 pcnt[p][tid] += 1;
@@ -276,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
             if (PER_EDGE && cjm) atomicAdd(&seg_cjm[q], cjm);
         }
         __syncthreads();
-        // per-wedge counters
+        // per-wedge counters (single-graph launches only)
         if (PER_WEDGE || PER_EDGE) {
             if (tid < nseg) {
                 const int64_t e = base + item.jb + tid;
@@ -298,82 +290,51 @@ __global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
         }
         // keep the per-lane 32-bit counters far from overflow
         if (block_probes > (1ull << 31)) {
-            __syncthreads();
-            if (tid < 21) {
-                unsigned long long s = 0;
-                for (int l = 0; l < kBlock; l++) s += pcnt[tid][l];
-                pacc[tid] += s;
-            }
-            __syncthreads();
-            for (int p = 0; p < 21; p++) pcnt[p][tid] = 0;
+            flush_counts(pcnt, A.counts, cur_g, tid);
             block_probes = 0;
         }
     }
-    __syncthreads();
-    if (tid < 21) {
-        unsigned long long s = pacc[tid];
-        for (int l = 0; l < kBlock; l++) s += pcnt[tid][l];
-        A.partials[(int64_t)blockIdx.x * 22 + tid] = s;
-    }
-    if (tid == 0) A.partials[(int64_t)blockIdx.x * 22 + 21] = all_probes;
+    if (cur_g >= 0) flush_counts(pcnt, A.counts, cur_g, tid);
+    if (tid == 0 && all_probes) atomicAdd(A.probes, all_probes);
 }
 
 // number of items per owner
-template <int CAP>
-__global__ void k_item_counts(const int64_t *fptr, int64_t m, int64_t *cnt) {
+__global__ void k_item_counts(const int64_t *fptr, int64_t m, int cap, int jp, int64_t *cnt) {
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
          r += (int64_t)gridDim.x * blockDim.x) {
         int64_t d = fptr[r + 1] - fptr[r];
         int64_t c = 0;
         if (d >= 2) {
-            for (int64_t cb = 0; cb < d; cb += CAP) {
-                int64_t ce = cb + CAP < d ? cb + CAP : d;
-                int64_t jend = ce - 1;
-                c += (jend + kJPiece - 1) / kJPiece;
+            for (int64_t cb = 0; cb < d; cb += cap) {
+                int64_t ce = cb + cap < d ? cb + cap : d;
+                c += (ce - 1 + jp - 1) / jp;
             }
         }
         cnt[r] = c;
     }
 }
 
-template <int CAP>
-__global__ void k_item_fill(const int64_t *fptr, int64_t m, const int64_t *ioff, Item *items) {
+__global__ void k_item_fill(const int64_t *fptr, int64_t m, int cap, int jp, int32_t gid, const int64_t *ioff,
+                            Item *items) {
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
          r += (int64_t)gridDim.x * blockDim.x) {
         int64_t d = fptr[r + 1] - fptr[r];
         if (d < 2) continue;
         int64_t o = ioff[r];
-        for (int64_t cb = 0; cb < d; cb += CAP) {
-            int64_t ce = cb + CAP < d ? cb + CAP : d;
+        for (int64_t cb = 0; cb < d; cb += cap) {
+            int64_t ce = cb + cap < d ? cb + cap : d;
             int64_t jend = ce - 1;
-            for (int64_t jb = 0; jb < jend; jb += kJPiece) {
+            for (int64_t jb = 0; jb < jend; jb += jp) {
                 Item it;
+                it.g = gid;
                 it.r = (int32_t)r;
                 it.cb = (int32_t)cb;
                 it.ce = (int32_t)ce;
                 it.jb = (int32_t)jb;
-                it.je = (int32_t)(jb + kJPiece < jend ? jb + kJPiece : jend);
+                it.je = (int32_t)(jb + jp < jend ? jb + jp : jend);
                 items[o++] = it;
             }
         }
-    }
-}
-
-// counts[0..20] patterns (counts[0] = total), counts[21] = entries probed
-__global__ void k_reduce_partials(const unsigned long long *partials, int nblocks, long long *counts) {
-    __shared__ unsigned long long s[22];
-    if (threadIdx.x < 22) {
-        unsigned long long acc = 0;
-        for (int b = 0; b < nblocks; b++) acc += partials[(int64_t)b * 22 + threadIdx.x];
-        s[threadIdx.x] = acc;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long tot = 0;
-        for (int p = 1; p <= 20; p++) tot += s[p];
-        counts[0] = (long long)tot;
-        for (int p = 1; p <= 20; p++) counts[p] = (long long)s[p];
-        counts[21] = (long long)s[21];
     }
 }
 
@@ -419,21 +380,89 @@ __global__ void k_rank_to_norm_u64(const unsigned long long *t, const int32_t *n
         out[norm_of_rank[r]] = (int64_t)t[r];
 }
 
-template <int CAP, bool PE, bool PW>
-int occupancy_blocks() {
+template <int CAP, int JP, bool PE, bool PW>
+int occ_blocks() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_close<CAP, PE, PW>, kBlock, 0) != hipSuccess || nb < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_close<CAP, JP, PE, PW>, kBlock, 0) != hipSuccess || nb < 1)
         nb = 1;
     return nb;
 }
 
-template <int CAP, bool PE, bool PW>
-void launch_close(const CloseArgs &a, int nblocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_close<CAP, PE, PW>), dim3(nblocks), dim3(kBlock), 0, s, a);
-    HTRI_LAUNCH_CHECK();
-}
+template <int CAP, int JP>
+struct CloseVariants {
+    static int blocks(bool pe, bool pw) {
+        return pe ? (pw ? occ_blocks<CAP, JP, true, true>() : occ_blocks<CAP, JP, true, false>())
+                  : (pw ? occ_blocks<CAP, JP, false, true>() : occ_blocks<CAP, JP, false, false>());
+    }
+    static void launch(bool pe, bool pw, const CloseArgs &a, int nb, hipStream_t s) {
+        if (pe && pw) hipLaunchKernelGGL((k_close<CAP, JP, true, true>), dim3(nb), dim3(kBlock), 0, s, a);
+        else if (pe) hipLaunchKernelGGL((k_close<CAP, JP, true, false>), dim3(nb), dim3(kBlock), 0, s, a);
+        else if (pw) hipLaunchKernelGGL((k_close<CAP, JP, false, true>), dim3(nb), dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL((k_close<CAP, JP, false, false>), dim3(nb), dim3(kBlock), 0, s, a);
+        HTRI_LAUNCH_CHECK();
+    }
+};
 
 }  // namespace
+
+bool valid_config(const CloseConfig &c) {
+    return (c.cap == 256 || c.cap == 512) && (c.jp == 128 || c.jp == 256);
+}
+
+int close_blocks_per_cu(const CloseConfig &c, bool pe, bool pw) {
+    if (c.cap == 256 && c.jp == 128) return CloseVariants<256, 128>::blocks(pe, pw);
+    if (c.cap == 256 && c.jp == 256) return CloseVariants<256, 256>::blocks(pe, pw);
+    if (c.cap == 512 && c.jp == 128) return CloseVariants<512, 128>::blocks(pe, pw);
+    if (c.cap == 512 && c.jp == 256) return CloseVariants<512, 256>::blocks(pe, pw);
+    fail(HTRI_E_INVALID, "unsupported closure configuration");
+    return 0;
+}
+
+void launch_close_kernel(const CloseConfig &c, bool pe, bool pw, const CloseArgs &a, int nb, hipStream_t s) {
+    if (c.cap == 256 && c.jp == 128) return CloseVariants<256, 128>::launch(pe, pw, a, nb, s);
+    if (c.cap == 256 && c.jp == 256) return CloseVariants<256, 256>::launch(pe, pw, a, nb, s);
+    if (c.cap == 512 && c.jp == 128) return CloseVariants<512, 128>::launch(pe, pw, a, nb, s);
+    if (c.cap == 512 && c.jp == 256) return CloseVariants<512, 256>::launch(pe, pw, a, nb, s);
+    fail(HTRI_E_INVALID, "unsupported closure configuration");
+}
+
+GraphDesc graph_desc(const Graph &g) {
+    GraphDesc d{};
+    d.fptr = g.fptr.p;
+    d.fadj = g.fadj.p;
+    d.mptr = g.mptr.p;
+    d.fmask = g.fmask.p;
+    d.esize = g.esize.p;
+    d.eptr = g.eptr.p;
+    d.emem = g.emem.p;
+    d.wbits = g.wbits;
+    return d;
+}
+
+int64_t build_items(Graph &g, int32_t gid, const CloseConfig &cfg, DBuf<Item> &out) {
+    hipStream_t s = g.stream;
+    Allocator &A = g.al;
+    const int64_t m = g.m;
+    DBuf<int64_t> icnt(A, m + 1);
+    if (m > 0) {
+        hipLaunchKernelGGL(k_item_counts, dim3(grid_for(m, 256)), dim3(256), 0, s, g.fptr.p, m, cfg.cap, cfg.jp,
+                           icnt.p);
+        HTRI_LAUNCH_CHECK();
+    }
+    scan_exclusive_i64(A, icnt.p, icnt.p, m, icnt.p + m, s);
+    int64_t nitems = 0;
+    HTRI_HIP(hipMemcpyAsync(&nitems, icnt.p + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HTRI_HIP(hipStreamSynchronize(s));
+    if (nitems >= (int64_t)UINT32_MAX) fail(HTRI_E_UNSUPPORTED, "too many work items");
+    out.alloc(A, nitems);
+    if (m > 0 && nitems > 0) {
+        hipLaunchKernelGGL(k_item_fill, dim3(grid_for(m, 256)), dim3(256), 0, s, g.fptr.p, m, cfg.cap, cfg.jp, gid,
+                           icnt.p, out.p);
+        HTRI_LAUNCH_CHECK();
+    }
+    HTRI_HIP(hipStreamSynchronize(s));
+    return nitems;
+}
 
 // ---------------------------------------------------------------- LUT
 
@@ -514,12 +543,11 @@ const uint8_t *pattern_lut() {
 
 // ---------------------------------------------------------------- driver
 
-constexpr int kCap = 512;
-
 void count_patterns(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev, uint32_t *cw_dev) {
     hipStream_t s = g.stream;
     Allocator &A = g.al;
     const int64_t m = g.m;
+    const CloseConfig cfg;  // 512-entry chunks, 256 partners per item
     hipEvent_t e0, e1, e2, e3;
     HTRI_HIP(hipEventCreate(&e0));
     HTRI_HIP(hipEventCreate(&e1));
@@ -527,27 +555,16 @@ void count_patterns(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev
     HTRI_HIP(hipEventCreate(&e3));
     HTRI_HIP(hipEventRecord(e0, s));
 
-    // schedule
-    DBuf<int64_t> icnt(A, m + 1);
-    if (m > 0) {
-        hipLaunchKernelGGL(k_item_counts<kCap>, dim3(grid_for(m, 256)), dim3(256), 0, s, g.fptr.p, m, icnt.p);
-        HTRI_LAUNCH_CHECK();
-    }
-    scan_exclusive_i64(A, icnt.p, icnt.p, m, icnt.p + m, s);
-    int64_t nitems = 0;
-    HTRI_HIP(hipMemcpyAsync(&nitems, icnt.p + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HTRI_HIP(hipStreamSynchronize(s));
-    if (nitems >= (int64_t)UINT32_MAX) fail(HTRI_E_UNSUPPORTED, "too many work items");
-    DBuf<Item> items(A, nitems);
-    if (m > 0) {
-        hipLaunchKernelGGL(k_item_fill<kCap>, dim3(grid_for(m, 256)), dim3(256), 0, s, g.fptr.p, m, icnt.p,
-                           items.p);
-        HTRI_LAUNCH_CHECK();
-    }
+    DBuf<Item> items;
+    const int64_t nitems = build_items(g, 0, cfg, items);
     DBuf<uint8_t> lut(A, 128);
     HTRI_HIP(hipMemcpyAsync(lut.p, pattern_lut(), 128, hipMemcpyHostToDevice, s));
-    DBuf<unsigned int> queue(A, 1);
-    fill_u32(queue.p, 1, 0, s);
+    DBuf<GraphDesc> desc(A, 1);
+    GraphDesc hd = graph_desc(g);
+    HTRI_HIP(hipMemcpyAsync(desc.p, &hd, sizeof(GraphDesc), hipMemcpyHostToDevice, s));
+    // counters: queue (1), pattern counts (21), probes (1), S (1)
+    DBuf<unsigned long long> ctr(A, 24);
+    fill_u64((uint64_t *)ctr.p, 24, 0, s);
 
     const bool pe = t_dev != nullptr;
     const bool pw = cw_dev != nullptr;
@@ -560,67 +577,61 @@ void count_patterns(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev
     }
     if (pw) fill_u32(cw_dev, g.nw, 0, s);
 
-    int per_cu = pe ? (pw ? occupancy_blocks<kCap, true, true>() : occupancy_blocks<kCap, true, false>())
-                    : (pw ? occupancy_blocks<kCap, false, true>() : occupancy_blocks<kCap, false, false>());
-    int nblocks = device_cu_count() * per_cu;
+    int nblocks = device_cu_count() * close_blocks_per_cu(cfg, pe, pw);
     if ((int64_t)nblocks > nitems) nblocks = (int)std::max<int64_t>(nitems, 1);
-    DBuf<unsigned long long> partials(A, (size_t)nblocks * 22);
+    HTRI_HIP(hipStreamSynchronize(s));
     HTRI_HIP(hipEventRecord(e1, s));
 
     CloseArgs a;
     a.items = items.p;
     a.nitems = nitems;
-    a.queue = queue.p;
-    a.fptr = g.fptr.p;
-    a.fadj = g.fadj.p;
-    a.mptr = g.mptr.p;
-    a.fmask = g.fmask.p;
-    a.esize = g.esize.p;
-    a.eptr = g.eptr.p;
-    a.emem = g.emem.p;
-    a.wbits = g.wbits;
+    a.queue = (unsigned int *)ctr.p;
+    a.graphs = desc.p;
     a.emask = mask;
     a.lut = lut.p;
     a.cwj = cw_dev;
     a.cwjm = cwjm.p;
     a.cwkm = cwkm.p;
-    a.partials = partials.p;
-    if (pe && pw) launch_close<kCap, true, true>(a, nblocks, s);
-    else if (pe) launch_close<kCap, true, false>(a, nblocks, s);
-    else if (pw) launch_close<kCap, false, true>(a, nblocks, s);
-    else launch_close<kCap, false, false>(a, nblocks, s);
+    a.counts = ctr.p + 1;
+    a.probes = ctr.p + 22;
+    launch_close_kernel(cfg, pe, pw, a, nblocks, s);
     HTRI_HIP(hipEventRecord(e2, s));
 
-    DBuf<long long> dcounts(A, 23);
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(64), 0, s, partials.p, nblocks, dcounts.p);
-    HTRI_LAUNCH_CHECK();
-    fill_u64((uint64_t *)(dcounts.p + 22), 1, 0, s);
     if (g.nw > 0) {
-        hipLaunchKernelGGL(k_stream_size, dim3(grid_for(g.nw, 256, 2048)), dim3(256), 0, s, g.fptr.p, g.fadj.p,
-                           g.nw, g.wbits, (unsigned long long *)(dcounts.p + 22));
+        hipLaunchKernelGGL(k_stream_size, dim3(grid_for(g.nw, 256, 2048)), dim3(256), 0, s, g.fptr.p, g.fadj.p, g.nw,
+                           g.wbits, ctr.p + 23);
         HTRI_LAUNCH_CHECK();
     }
     if (pe) {
         DBuf<unsigned long long> t(A, m);
         fill_u64((uint64_t *)t.p, m, 0, s);
         if (m > 0) {
-            hipLaunchKernelGGL(k_edge_counts, dim3(grid_for(m, 256)), dim3(256), 0, s, g.fptr.p, g.fadj.p, m,
-                               g.wbits, cwjm.p, cwkm.p, t.p);
+            hipLaunchKernelGGL(k_edge_counts, dim3(grid_for(m, 256)), dim3(256), 0, s, g.fptr.p, g.fadj.p, m, g.wbits,
+                               cwjm.p, cwkm.p, t.p);
             HTRI_LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_rank_to_norm_u64, dim3(grid_for(m, 256)), dim3(256), 0, s, t.p,
-                               g.norm_of_rank.p, m, (int64_t *)t_dev);
+            hipLaunchKernelGGL(k_rank_to_norm_u64, dim3(grid_for(m, 256)), dim3(256), 0, s, t.p, g.norm_of_rank.p, m,
+                               (int64_t *)t_dev);
             HTRI_LAUNCH_CHECK();
         }
+        HTRI_HIP(hipEventRecord(e3, s));
+        HTRI_HIP(hipStreamSynchronize(s));
+    } else {
+        HTRI_HIP(hipEventRecord(e3, s));
     }
-    HTRI_HIP(hipEventRecord(e3, s));
-    int64_t hc[23];
-    HTRI_HIP(hipMemcpyAsync(hc, dcounts.p, sizeof(int64_t) * 23, hipMemcpyDeviceToHost, s));
+    unsigned long long hc[24];
+    HTRI_HIP(hipMemcpyAsync(hc, ctr.p, sizeof(hc), hipMemcpyDeviceToHost, s));
     HTRI_HIP(hipStreamSynchronize(s));
-    std::memcpy(counts, hc, sizeof(int64_t) * 21);
+    int64_t tot = 0;
+    counts[0] = 0;
+    for (int p = 1; p <= 20; p++) {
+        counts[p] = (int64_t)hc[1 + p];
+        tot += counts[p];
+    }
+    counts[0] = tot;
     int64_t mask_words_total = 0;
     HTRI_HIP(hipMemcpy(&mask_words_total, g.mptr.p + m, sizeof(int64_t), hipMemcpyDeviceToHost));
-    g.cstats[0] = hc[22];
-    g.cstats[1] = hc[21];
+    g.cstats[0] = (int64_t)hc[23];
+    g.cstats[1] = (int64_t)hc[22];
     g.cstats[2] = nitems;
     g.cstats[3] = mask_words_total;
     g.cstats[4] = nblocks;

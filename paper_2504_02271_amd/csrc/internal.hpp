@@ -171,15 +171,56 @@ struct Graph {
     int64_t cstats[5] = {0, 0, 0, 0, 0};
 };
 
+// api.hip: message for htri_last_error(NULL)
+void set_load_error(const std::string &msg);
+
 // load.hip
 void graph_load(Graph &g, const int64_t *off, int64_t m_in, const int32_t *mem, int32_t n,
                 uint32_t flags);
 // wedges.hip
 void build_wedges(Graph &g);
 // closure.hip
-struct CountOut {
-    int64_t counts[21];
+// Read-only view of one graph's step-1 state, as the closure kernel sees it.
+struct GraphDesc {
+    const int64_t *fptr;
+    const uint32_t *fadj;
+    const int64_t *mptr;
+    const uint32_t *fmask;
+    const int32_t *esize;
+    const int64_t *eptr;
+    const int32_t *emem;
+    int32_t wbits;
+    int32_t pad;
 };
+// A closure work item: graph g, owner r, chunk [cb, ce) of N+(r), partner
+// positions [jb, je) of N+(r).
+struct Item {
+    int32_t g, r, cb, ce, jb, je;
+};
+// Chunk capacity (entries of N+(r) in LDS) and partners per item.
+struct CloseConfig {
+    int cap = 512;
+    int jp = 256;
+};
+struct CloseArgs {
+    const Item *items;
+    int64_t nitems;
+    unsigned int *queue;            // item counter, zero before the launch
+    const GraphDesc *graphs;
+    uint32_t emask;                 // patterns counted into per-edge counts
+    const uint8_t *lut;             // 128-entry region table
+    uint32_t *cwj;                  // per-wedge j-role count, all patterns (single graph)
+    uint32_t *cwjm;                 // per-wedge j-role count, masked
+    uint32_t *cwkm;                 // per-wedge k-role count, masked
+    unsigned long long *counts;     // [graphs][21]; [g][0] unused (total formed on the host)
+    unsigned long long *probes;     // entries probed
+};
+GraphDesc graph_desc(const Graph &g);
+// items of one graph (graph index gid) for a configuration
+int64_t build_items(Graph &g, int32_t gid, const CloseConfig &cfg, DBuf<Item> &out);
+int close_blocks_per_cu(const CloseConfig &cfg, bool pe, bool pw);
+void launch_close_kernel(const CloseConfig &cfg, bool pe, bool pw, const CloseArgs &a, int nblocks, hipStream_t s);
+bool valid_config(const CloseConfig &cfg);
 void count_patterns(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev /*m or null*/,
                     uint32_t *cw_dev /*nw or null*/);
 // sample.hip: closure of explicit wedges (per-sample counts) and weighted

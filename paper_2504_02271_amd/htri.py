@@ -55,6 +55,13 @@ class SampleParams(ctypes.Structure):
                 ("pool_factor", ctypes.c_double)]
 
 
+class Schedule(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int32), ("partners", ctypes.c_int32), ("order", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (int(self.chunk), int(self.partners), int(self.order))
+
+
 _lib = None
 
 
@@ -97,8 +104,12 @@ def load_library() -> ctypes.CDLL:
         "htri_model_forward": ([_P, _P, _i64, _P], ctypes.c_int),
         "htri_model_loss_grad": ([_P, _P, _P, _i64, _P, _P], ctypes.c_int),
         "htri_model_train": ([_P, _P, _P, _i64, _i32, _i32, ctypes.c_float, _u64, _P], ctypes.c_int),
-        "htri_batch_load": ([_i32, _P, _P, _P, _P, _u32, _P, ctypes.POINTER(_P)], ctypes.c_int),
-        "htri_batch_count": ([_P, _i32, _i32, _P, _P], ctypes.c_int),
+        "htri_batch_load": ([_i32, _P, _P, _P, _P, _u32, ctypes.POINTER(_P)], ctypes.c_int),
+        "htri_batch_info": ([_P, _P], ctypes.c_int),
+        "htri_batch_count": ([_P, ctypes.POINTER(Schedule), _i32, _P, _P], ctypes.c_int),
+        "htri_batch_autotune": ([_P, _i32, ctypes.POINTER(Schedule), _P], ctypes.c_int),
+        "htri_batch_count_per_graph": ([_P, ctypes.POINTER(Schedule), _P, _P], ctypes.c_int),
+        "htri_batch_last_error": ([_P], ctypes.c_char_p),
         "htri_batch_free": ([_P], None),
     }
     for name, (args, res) in _optional.items():
@@ -252,6 +263,35 @@ class Graph:
         _check(self._lib.htri_closure_stats(self._h, _ptr(out)), "htri_closure_stats", self._h)
         return out
 
+    def estimate(self, budget: float = 0.01, num_samples: int = 0, seed: int = 0, proposal: int = 0,
+                 model: "Optional[Model]" = None, defensive_mix: float = 0.1, pool_factor: float = 0.0):
+        """Hyperwedge-sampling estimate: (est float64[21], stderr float64[21], device ms)."""
+        p = SampleParams(float(budget), int(num_samples), int(seed) & 0xFFFFFFFFFFFFFFFF, int(proposal), 0,
+                         model._h if model is not None else None, float(defensive_mix), float(pool_factor))
+        est = np.zeros(21, np.float64)
+        se = np.zeros(21, np.float64)
+        ms = ctypes.c_double(0.0)
+        _check(self._lib.htri_estimate(self._h, ctypes.byref(p), _ptr(est), _ptr(se), ctypes.byref(ms)),
+               "htri_estimate", self._h)
+        return est, se, float(ms.value)
+
+    def close_wedges(self, idx) -> np.ndarray:
+        """Per-pattern closure counts int64[n, 21] of the listed wedges (get_wedges order)."""
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        out = np.zeros((idx.shape[0], 21), np.int64)
+        _check(self._lib.htri_close_wedges(self._h, _ptr(idx), idx.shape[0], _ptr(out)),
+               "htri_close_wedges", self._h)
+        return out
+
+    def wedge_features(self):
+        """float32 [|wedges|, 16] torch tensor on the GPU."""
+        import torch
+        x = torch.empty((max(self.num_wedges, 1), 16), dtype=torch.float32, device="cuda")
+        if self.num_wedges:
+            _check(self._lib.htri_wedge_features(self._h, ctypes.c_void_p(x.data_ptr())),
+                   "htri_wedge_features", self._h)
+        return x[: self.num_wedges]
+
     def last_timings(self) -> np.ndarray:
         ms = np.zeros(4, np.float64)
         _check(self._lib.htri_last_timings(self._h, _ptr(ms)), "htri_last_timings", self._h)
@@ -280,3 +320,136 @@ def graph_load(offsets, members, num_vertices: int, flags: int = HTRI_DEDUPE_EDG
     rc = lib.htri_graph_load(off_p, m, mem_p, int(num_vertices), flags, alloc, stream, ctypes.byref(h))
     _check(rc, "htri_graph_load", None)
     return Graph(h, mem)
+
+
+# ---------------------------------------------------------------- model
+
+class Model:
+    """The proposal network (htri_model): 16 -> 64 -> 64 -> 1, ReLU, float32."""
+
+    def __init__(self, seed: int = 0, mem: Optional[TorchMemory] = None):
+        self._lib = load_library()
+        mem = mem or default_memory()
+        h = ctypes.c_void_p()
+        _check(self._lib.htri_model_create(int(seed), mem.stream_handle(), ctypes.byref(h)), "htri_model_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.htri_model_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(HTRI_MODEL_NUM_PARAMS, np.float32)
+        _check(self._lib.htri_model_get_params(self._h, _ptr(out)), "htri_model_get_params")
+        return out
+
+    def set_params(self, params: np.ndarray) -> None:
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        assert params.shape == (HTRI_MODEL_NUM_PARAMS,)
+        _check(self._lib.htri_model_set_params(self._h, _ptr(params)), "htri_model_set_params")
+
+    def forward(self, x):
+        import torch
+        x = x.contiguous()
+        out = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        _check(self._lib.htri_model_forward(self._h, ctypes.c_void_p(x.data_ptr()), x.shape[0],
+                                            ctypes.c_void_p(out.data_ptr())), "htri_model_forward")
+        return out
+
+    def loss_grad(self, x, y):
+        x = x.contiguous()
+        y = y.contiguous()
+        g = np.zeros(HTRI_MODEL_NUM_PARAMS, np.float32)
+        L = ctypes.c_double(0.0)
+        _check(self._lib.htri_model_loss_grad(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                              x.shape[0], ctypes.byref(L), _ptr(g)), "htri_model_loss_grad")
+        return float(L.value), g
+
+    def train(self, x, y, steps: int, batch: int = 4096, lr: float = 1e-3, seed: int = 0) -> float:
+        x = x.contiguous()
+        y = y.contiguous()
+        L = ctypes.c_double(0.0)
+        _check(self._lib.htri_model_train(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                          x.shape[0], int(steps), int(batch), float(lr), int(seed),
+                                          ctypes.byref(L)), "htri_model_train")
+        return float(L.value)
+
+
+# ---------------------------------------------------------------- batch
+
+class Batch:
+    """Many hypergraphs counted in one persistent launch (htri_batch)."""
+
+    def __init__(self, graphs, flags: int = HTRI_DEDUPE_EDGES):
+        self._lib = load_library()
+        n = len(graphs)
+        self._keep = []
+        offs = (ctypes.c_void_p * max(n, 1))()
+        mems = (ctypes.c_void_p * max(n, 1))()
+        ne = np.zeros(max(n, 1), np.int64)
+        nv = np.zeros(max(n, 1), np.int32)
+        for q, g in enumerate(graphs):
+            o = np.ascontiguousarray(g.offsets, dtype=np.int64)
+            m = np.ascontiguousarray(g.members, dtype=np.int32)
+            self._keep += [o, m]
+            offs[q] = o.ctypes.data
+            mems[q] = m.ctypes.data
+            ne[q] = o.shape[0] - 1
+            nv[q] = g.num_vertices
+        h = ctypes.c_void_p()
+        rc = self._lib.htri_batch_load(n, offs, _ptr(ne), mems, _ptr(nv), flags, ctypes.byref(h))
+        _check(rc, "htri_batch_load", None)
+        self._h = h
+        self.count = n
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.htri_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, rc, where):
+        if rc != HTRI_OK:
+            msg = self._lib.htri_batch_last_error(self._h)
+            raise HtriError(rc, where, msg.decode() if msg else "")
+
+    def wedges(self) -> np.ndarray:
+        out = np.zeros(self.count, np.int64)
+        self._err(self._lib.htri_batch_info(self._h, _ptr(out)), "htri_batch_info")
+        return out
+
+    def count_patterns(self, schedule=(512, 256, 0), use_graph: bool = True):
+        sc = Schedule(*schedule)
+        out = np.zeros((self.count, 21), np.int64)
+        ms = ctypes.c_double(0.0)
+        self._err(self._lib.htri_batch_count(self._h, ctypes.byref(sc), 1 if use_graph else 0, _ptr(out),
+                                             ctypes.byref(ms)), "htri_batch_count")
+        return out, float(ms.value)
+
+    def autotune(self, repeats: int = 2):
+        sc = Schedule(0, 0, 0)
+        ms = ctypes.c_double(0.0)
+        self._err(self._lib.htri_batch_autotune(self._h, int(repeats), ctypes.byref(sc), ctypes.byref(ms)),
+                  "htri_batch_autotune")
+        return sc.as_tuple(), float(ms.value)
+
+    def count_per_graph(self, schedule=(512, 256, 0)):
+        sc = Schedule(*schedule)
+        out = np.zeros((self.count, 21), np.int64)
+        ms = ctypes.c_double(0.0)
+        self._err(self._lib.htri_batch_count_per_graph(self._h, ctypes.byref(sc), _ptr(out), ctypes.byref(ms)),
+                  "htri_batch_count_per_graph")
+        return out, float(ms.value)

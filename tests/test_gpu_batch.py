@@ -1,0 +1,75 @@
+"""Batched counting: one persistent launch over many hypergraphs, replayed
+from a captured HIP graph, against per-graph counts and the oracle."""
+import numpy as np
+import pytest
+
+from oracle import core
+from paper_2504_02271_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def htri():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2504_02271_amd import htri as h
+    h.load_library()
+    return h
+
+
+@pytest.fixture(scope="module")
+def small_batch():
+    specs = synth.batch_specs(num_graphs=24, e_lo=300, e_hi=6000)
+    graphs = [synth.generate(s) for s in specs]
+    graphs.append(synth.random_small(3, 70, 10, 1, 6))      # every pattern
+    graphs.append(synth.from_lists([[0, 1]], 2, "single"))   # no hyperwedge
+    return graphs
+
+
+def test_batch_matches_oracle_and_per_graph(htri, small_batch):
+    B = htri.Batch(small_batch)
+    want = np.array([core.OracleGraph(g.offsets, g.members, g.num_vertices).count(per_edge=False).H
+                     for g in small_batch])
+    for sched in ((512, 256, 0), (256, 128, 1), (512, 128, 1), (256, 256, 0)):
+        got, ms = B.count_patterns(sched, use_graph=False)
+        assert np.array_equal(got, want), sched
+        per, ms2 = B.count_per_graph(sched)
+        assert np.array_equal(per, want), sched
+    nw = B.wedges()
+    for g, x in zip(small_batch, nw):
+        G = htri.graph_load(g.offsets, g.members, g.num_vertices)
+        assert G.build_wedges()[0] == x
+
+
+def test_graph_replays_agree_with_eager(htri, small_batch):
+    """Replay the captured launch several times, with eager work and
+    synchronisations in between; every replay gives the eager counts."""
+    import torch
+    B = htri.Batch(small_batch)
+    eager, _ = B.count_patterns((512, 256, 1), use_graph=False)
+    x = torch.arange(1 << 16, device="cuda", dtype=torch.float32)
+    for r in range(5):
+        got, ms = B.count_patterns((512, 256, 1), use_graph=True)
+        assert np.array_equal(got, eager), r
+        y = (x * r).sum().item()                       # eager work between replays
+        torch.cuda.synchronize()
+        assert y >= 0
+
+
+def test_autotune_picks_a_valid_schedule(htri, small_batch):
+    B = htri.Batch(small_batch[:8])
+    sched, ms = B.autotune(repeats=1)
+    assert sched[0] in (256, 512) and sched[1] in (128, 256) and sched[2] in (0, 1)
+    assert ms > 0
+    got, _ = B.count_patterns(sched)
+    want = np.array([core.OracleGraph(g.offsets, g.members, g.num_vertices).count(per_edge=False).H
+                     for g in small_batch[:8]])
+    assert np.array_equal(got, want)
+
+
+def test_batch_load_errors(htri):
+    bad = synth.from_lists([[0, 1], [1, 0]], 2)
+    with pytest.raises(htri.HtriError) as e:
+        htri.Batch([synth.from_lists([[0, 1], [1, 2]], 3), bad], flags=0)
+    assert e.value.code == -4 and "graph 1" in str(e.value)
