@@ -70,16 +70,12 @@ __device__ __forceinline__ uint32_t region_mask(int si, int sj, int sk, int wij,
            ((uint32_t)(e > 0) << 4) | ((uint32_t)(f > 0) << 5) | ((uint32_t)(g > 0) << 6);
 }
 
-// Add the per-lane pattern counters to counts[g] and clear them.
-__device__ __forceinline__ void flush_counts(uint32_t (*pcnt)[kBlock], unsigned long long *counts, int g, int tid) {
-    __syncthreads();
-    if (tid >= 1 && tid < 21) {
-        unsigned long long s = 0;
-        for (int l = 0; l < kBlock; l++) s += pcnt[tid][l];
-        if (s) atomicAdd(&counts[(int64_t)g * 21 + tid], s);
-    }
-    __syncthreads();
-    for (int p = 0; p < 21; p++) pcnt[p][tid] = 0;
+// Each lane p (1..20) of a wave holds the wave's count of pattern p; add
+// them to counts[g] and clear.
+__device__ __forceinline__ void flush_wave_counts(unsigned long long &wcnt, unsigned long long *counts, int g,
+                                                  int lane) {
+    if (lane >= 1 && lane < 21 && wcnt) atomicAdd(&counts[(int64_t)g * 21 + lane], wcnt);
+    wcnt = 0;
 }
 
 template <int CAP, int JP, bool PER_EDGE, bool PER_WEDGE>
@@ -97,15 +93,14 @@ __global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
     __shared__ uint32_t seg_mask[JP * kMaskWordsMax];
     __shared__ uint32_t seg_cj[PER_WEDGE ? JP : 1];
     __shared__ uint32_t seg_cjm[PER_EDGE ? JP : 1];
-    __shared__ uint32_t pcnt[21][kBlock];
     __shared__ uint8_t lut[128];
     __shared__ int64_t sh_item;
     __shared__ int64_t sh_scan[kBlock / kWave + 1];
 
     const int tid = threadIdx.x;
-    for (int p = 0; p < 21; p++) pcnt[p][tid] = 0;
+    const int lane = tid & (kWave - 1);
     if (tid < 128) lut[tid] = A.lut[tid];
-    uint64_t block_probes = 0;
+    unsigned long long wcnt = 0;     // lane p: this wave's count of pattern p
     unsigned long long all_probes = 0;
     int cur_g = -1;
 
@@ -120,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
         if (it < 0) break;
         const Item item = A.items[it];
         if (item.g != cur_g) {
-            if (cur_g >= 0) flush_counts(pcnt, A.counts, cur_g, tid);
+            if (cur_g >= 0) flush_wave_counts(wcnt, A.counts, cur_g, lane);
             cur_g = item.g;
         }
         const GraphDesc G = A.graphs[item.g];
@@ -177,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
         }
         // exclusive scan of segment lengths
         {
-            const int lane = tid & (kWave - 1), wave = tid / kWave;
+            const int wave = tid / kWave;
             int64_t incl = len;
 #pragma unroll
             for (int o = 1; o < kWave; o <<= 1) {
@@ -201,7 +196,6 @@ __global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
         }
         __syncthreads();
         const int64_t total = seg_pre[kBlock];
-        block_probes += (uint64_t)total;
         all_probes += (unsigned long long)total;
 
         // stream the partner lists through the hash
@@ -211,56 +205,72 @@ __global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
         int64_t src = 0;
         uint32_t cj = 0, cjm = 0;
         int32_t jrank = 0;
-        for (int64_t f = tid; f < total; f += kBlock) {
-            if (q < 0 || seg_pre[q + 1] <= f) {
-                if (q >= 0) {
-                    if (PER_WEDGE && cj) atomicAdd(&seg_cj[q], cj);
-                    if (PER_EDGE && cjm) atomicAdd(&seg_cjm[q], cjm);
-                }
-                cj = cjm = 0;
-                int lo_s = q < 0 ? 0 : q + 1, hi_s = nseg;
-                while (lo_s < hi_s) {
-                    int mid = (lo_s + hi_s) >> 1;
-                    if (seg_pre[mid + 1] <= f) lo_s = mid + 1; else hi_s = mid;
-                }
-                q = lo_s;
-                sj = (int)seg_size[q];
-                wij = (int)seg_om[q];
+        // wave-uniform loop: lane l of the wave takes entry fb + l
+        for (int64_t fb = tid - lane; fb < total; fb += kBlock) {
+            const int64_t f = fb + lane;
+            const bool valid = f < total;
+            bool hit = false;
+            uint32_t p = 0;
+            if (valid) {
+                if (q < 0 || seg_pre[q + 1] <= f) {
+                    if (q >= 0) {
+                        if (PER_WEDGE && cj) atomicAdd(&seg_cj[q], cj);
+                        if (PER_EDGE && cjm) atomicAdd(&seg_cjm[q], cjm);
+                    }
+                    cj = cjm = 0;
+                    int lo_s = q < 0 ? 0 : q + 1, hi_s = nseg;
+                    while (lo_s < hi_s) {
+                        int mid = (lo_s + hi_s) >> 1;
+                        if (seg_pre[mid + 1] <= f) lo_s = mid + 1; else hi_s = mid;
+                    }
+                    q = lo_s;
+                    sj = (int)seg_size[q];
+                    wij = (int)seg_om[q];
 #pragma unroll
-                for (int w = 0; w < kMaskWordsMax; w++) mj[w] = w < W ? seg_mask[q * kMaskWordsMax + w] : 0u;
-                src = seg_src[q] - seg_pre[q];
-                jrank = (int32_t)(G.fadj[base + item.jb + q] >> G.wbits);
-            }
-            const uint32_t ent = G.fadj[src + f];
-            const uint32_t k = ent >> G.wbits;
-            uint32_t slot = hslot(k, hbits);
-            uint64_t v;
-            for (;;) {
-                v = tab[slot];
-                if (v == kEmpty || ((uint32_t)v >> G.wbits) == k) break;
-                slot = (slot + 1) & (H - 1);
-            }
-            if (v != kEmpty) {
-                const uint32_t pos = (uint32_t)(v >> 32);
-                const int wik = (int)((uint32_t)v & wmask);
-                const int wjk = (int)(ent & wmask);
-                const int sk = (int)ent_size[pos];
-                int g;
-                if (W > 0) {
-                    g = 0;
+                    for (int w = 0; w < kMaskWordsMax; w++) mj[w] = w < W ? seg_mask[q * kMaskWordsMax + w] : 0u;
+                    src = seg_src[q] - seg_pre[q];
+                    if (W == 0) jrank = (int32_t)(G.fadj[base + item.jb + q] >> G.wbits);
+                }
+                const uint32_t ent = G.fadj[src + f];
+                const uint32_t k = ent >> G.wbits;
+                uint32_t slot = hslot(k, hbits);
+                uint64_t v;
+                for (;;) {
+                    v = tab[slot];
+                    if (v == kEmpty || ((uint32_t)v >> G.wbits) == k) break;
+                    slot = (slot + 1) & (H - 1);
+                }
+                if (v != kEmpty) {
+                    const uint32_t pos = (uint32_t)(v >> 32);
+                    const int wik = (int)((uint32_t)v & wmask);
+                    const int wjk = (int)(ent & wmask);
+                    const int sk = (int)ent_size[pos];
+                    int g;
+                    if (W > 0) {
+                        g = 0;
 #pragma unroll
-                    for (int w = 0; w < kMaskWordsMax; w++)
-                        if (w < W) g += __popc(mj[w] & ent_mask[pos * kMaskWordsMax + w]);
-                } else {
-                    g = triple_common(G.eptr, G.emem, r, jrank, (int32_t)k);
+                        for (int w = 0; w < kMaskWordsMax; w++)
+                            if (w < W) g += __popc(mj[w] & ent_mask[pos * kMaskWordsMax + w]);
+                    } else {
+                        g = triple_common(G.eptr, G.emem, r, jrank, (int32_t)k);
+                    }
+                    p = lut[region_mask(si, sj, sk, wij, wik, wjk, g)];
+                    hit = true;
+                    cj++;
+                    if (PER_EDGE && ((A.emask >> p) & 1u)) {
+                        cjm++;
+                        atomicAdd(&ent_ck[pos], 1u);
+                    }
                 }
-                const uint32_t p = lut[region_mask(si, sj, sk, wij, wik, wjk, g)];
-                pcnt[p][tid] += 1;
-                cj++;
-                if (PER_EDGE && ((A.emask >> p) & 1u)) {
-                    cjm++;
-                    atomicAdd(&ent_ck[pos], 1u);
-                }
+            }
+            // aggregate the wave's hits by pattern into lane p
+            uint64_t pend = __ballot(hit);
+            while (pend) {
+                const int srcl = __ffsll((unsigned long long)pend) - 1;
+                const uint32_t p0 = (uint32_t)__shfl((int)p, srcl, kWave);
+                const uint64_t mm = __ballot(hit && p == p0);
+                if ((uint32_t)lane == p0) wcnt += (unsigned long long)__popcll(mm);
+                pend &= ~mm;
             }
         }
         if (q >= 0) {
@@ -288,13 +298,8 @@ __global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
                 }
             }
         }
-        // keep the per-lane 32-bit counters far from overflow
-        if (block_probes > (1ull << 31)) {
-            flush_counts(pcnt, A.counts, cur_g, tid);
-            block_probes = 0;
-        }
     }
-    if (cur_g >= 0) flush_counts(pcnt, A.counts, cur_g, tid);
+    if (cur_g >= 0) flush_wave_counts(wcnt, A.counts, cur_g, lane);
     if (tid == 0 && all_probes) atomicAdd(A.probes, all_probes);
 }
 

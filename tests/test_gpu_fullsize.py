@@ -1,0 +1,73 @@
+"""Parity at the full benchmark size (tags-shaped, |V|=1e6, |E|=5e6, the
+launch configuration bench.py times): per-wedge closures and per-hyperedge
+counts on samples the oracle computes one by one, and invariants of the
+whole count."""
+import numpy as np
+import pytest
+
+from oracle import core
+from paper_2504_02271_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def full():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2504_02271_amd import htri
+    g = synth.generate(synth.config("tags"))
+    print(f"\n[fullsize] tags: {g.num_edges} hyperedges, {g.nnz} memberships", flush=True)
+    G = htri.graph_load(g.offsets, g.members, g.num_vertices)
+    s = G.build_wedges()
+    counts, pe, pw = G.count_patterns(per_edge=True, per_wedge=True)
+    print(f"[fullsize] wedges {int(s[0])} triangles {int(counts[0])} stages ms {G.last_timings().tolist()}",
+          flush=True)
+    src, dst, om = G.get_wedges()
+    o = core.OracleGraph(g.offsets, g.members, g.num_vertices)
+    off, mem, orig = o.csr()
+    rank = core.prec_rank(off, mem, g.num_vertices)
+    return dict(g=g, G=G, s=s, counts=counts, pe=pe, pw=pw, src=src, dst=dst, om=om, o=o, off=off, mem=mem,
+                rank=rank)
+
+
+def test_invariants(full):
+    counts, pe, pw, s = full["counts"], full["pe"], full["pw"], full["s"]
+    assert counts[1:].sum() == counts[0] > 0
+    assert int(pe.sum()) == 3 * int(counts[0])
+    assert int(pw.astype(np.int64).sum()) == int(counts[0])
+    assert 3 * int(counts[0]) <= int(s[3])
+    assert s[1] + s[2] == s[0]
+    # orientation: every stored wedge goes forward in the order
+    rank = full["rank"]
+    idx = np.random.default_rng(0).choice(full["src"].shape[0], size=200000, replace=False)
+    assert (rank[full["src"][idx]] < rank[full["dst"][idx]]).all()
+
+
+def test_sampled_wedge_closures(full):
+    """Per-wedge closure counts (all patterns) on 400 uniform wedges and the
+    60 wedges with the largest closure, against the oracle."""
+    pw, src, dst = full["pw"], full["src"], full["dst"]
+    rng = np.random.default_rng(1)
+    idx = np.concatenate([rng.choice(src.shape[0], size=400, replace=False),
+                          np.argpartition(pw, -60)[-60:]])
+    print(f"\n[fullsize] oracle closure of {idx.shape[0]} wedges", flush=True)
+    want = full["o"].wedge_closure_ranked(full["rank"], src[idx], dst[idx])
+    assert np.array_equal(pw[idx].astype(np.int64), want[:, 0])
+    # the per-pattern split of the same wedges through the sampling kernel
+    got = full["G"].close_wedges(idx)
+    assert np.array_equal(got, want)
+
+
+def test_sampled_hyperedge_counts(full):
+    """Per-hyperedge counts on 150 light hyperedges and 2 of moderate degree."""
+    pe = full["pe"]
+    o = full["o"]
+    deg = np.bincount(full["src"], minlength=o.m) + np.bincount(full["dst"], minlength=o.m)
+    rng = np.random.default_rng(2)
+    light = np.flatnonzero(deg <= 60)
+    mid = np.flatnonzero((deg > 200) & (deg <= 600))
+    xs = np.concatenate([rng.choice(light, size=150, replace=False), rng.choice(mid, size=2, replace=False)])
+    print(f"\n[fullsize] oracle triangles of {xs.shape[0]} hyperedges", flush=True)
+    want = o.edge_triangles(xs)
+    assert np.array_equal(pe[xs], want)
