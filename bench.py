@@ -92,6 +92,8 @@ def main() -> int:
     ap.add_argument("--workload", default="tags", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -118,6 +120,16 @@ def main() -> int:
     load_ms = (time.time() - t0) * 1e3
     log(f"[bench] loaded + normalised on the GPU in {load_ms:.1f} ms (incl. host-to-device copy); "
         f"{G.num_edges} hyperedges kept, {G.removed} duplicates removed")
+
+    if args.copy_calibration_mib > 0:
+        nb = args.copy_calibration_mib << 20
+        src = torch.empty(nb // 4, dtype=torch.int32, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: {nb} bytes read and written once")
+        del src, dst
 
     def step():
         G.clear_wedges()

@@ -26,14 +26,22 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kMaskWordsMax = 4;
-constexpr uint64_t kEmpty = ~0ull;
+constexpr uint32_t kEmptyPos = 0xFFFFFFFFu;
 
 __host__ __device__ __forceinline__ int mask_words(int size) {
     return size <= 32 * kMaskWordsMax ? (size + 31) / 32 : 0;
 }
 
 __device__ __forceinline__ uint32_t hslot(uint32_t k, int hbits) {
-    return (k * 0x9E3779B1u) >> (32 - hbits);
+    // full-rate 24x24-bit multiply by a golden-ratio constant, top bits
+    return (uint32_t)__umul24(k ^ (k >> 24), 0x9E3779u) >> (32 - hbits);   // __umul24 returns int
+}
+
+// Loads through the global address space (the graph's arrays reach the
+// kernel through a descriptor, so the compiler cannot infer it).
+template <typename T>
+__device__ __forceinline__ T gld(const T *p) {
+    return *(const __attribute__((address_space(1))) T *)p;
 }
 
 // first index in [a, b) whose entry's rank is >= key
@@ -41,7 +49,7 @@ __device__ __forceinline__ int64_t lower_rank(const uint32_t *fadj, int64_t a, i
                                               int wbits) {
     while (a < b) {
         int64_t mid = a + ((b - a) >> 1);
-        if ((fadj[mid] >> wbits) < key) a = mid + 1; else b = mid;
+        if ((gld(fadj + mid) >> wbits) < key) a = mid + 1; else b = mid;
     }
     return a;
 }
@@ -49,10 +57,11 @@ __device__ __forceinline__ int64_t lower_rank(const uint32_t *fadj, int64_t a, i
 // |e_r & e_j & e_k| by a three-way merge of sorted member lists (hyperedges
 // too large for stored masks)
 __device__ int triple_common(const int64_t *eptr, const int32_t *emem, int32_t r, int32_t j, int32_t k) {
-    int64_t a = eptr[r], ae = eptr[r + 1], b = eptr[j], be = eptr[j + 1], c = eptr[k], ce = eptr[k + 1];
+    int64_t a = gld(eptr + r), ae = gld(eptr + r + 1), b = gld(eptr + j), be = gld(eptr + j + 1),
+            c = gld(eptr + k), ce = gld(eptr + k + 1);
     int cnt = 0;
     while (a < ae && b < be && c < ce) {
-        int32_t x = emem[a], y = emem[b], z = emem[c];
+        int32_t x = gld(emem + a), y = gld(emem + b), z = gld(emem + c);
         if (x == y && y == z) { cnt++; a++; b++; c++; continue; }
         int32_t mx = x > y ? x : y;
         mx = mx > z ? mx : z;
@@ -70,21 +79,121 @@ __device__ __forceinline__ uint32_t region_mask(int si, int sj, int sk, int wij,
            ((uint32_t)(e > 0) << 4) | ((uint32_t)(f > 0) << 5) | ((uint32_t)(g > 0) << 6);
 }
 
-// Each lane p (1..20) of a wave holds the wave's count of pattern p; add
-// them to counts[g] and clear.
-__device__ __forceinline__ void flush_wave_counts(unsigned long long &wcnt, unsigned long long *counts, int g,
-                                                  int lane) {
+// Emptiness mask of the common-vertex pattern: the three private regions and
+// the triple region non-empty, the three pair-only regions empty.
+constexpr uint32_t kMaskCommonVertex = 0x47;
+constexpr uint32_t kPatternCommonVertex = 9;
+
+// Each lane p (1..20) of a wave holds the wave's count of pattern p, and
+// every lane a share of the common-vertex pattern's count; add them to
+// counts[g] and clear.
+__device__ __forceinline__ void flush_wave_counts(unsigned long long &wcnt, unsigned long long &c9,
+                                                  unsigned long long *counts, int g, int lane) {
+    unsigned long long s9 = c9;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s9 += __shfl_xor(s9, o, kWave);
+    if (lane == (int)kPatternCommonVertex) wcnt += s9;
     if (lane >= 1 && lane < 21 && wcnt) atomicAdd(&counts[(int64_t)g * 21 + lane], wcnt);
     wcnt = 0;
+    c9 = 0;
+}
+
+constexpr int kUnroll = 4;   // partner-list entries per lane per step
+
+// Find the slot of key kk = (k << wbits) in the bucketed open-addressing
+// table (two (entry, position) slots per 16-byte bucket, buckets probed
+// linearly; a bucket's second slot fills after its first).  Returns whether
+// it is present; slot in out.
+__device__ __forceinline__ bool lookup(const uint2 *tab, uint32_t kk, uint32_t kmask, int wbits, int hbits,
+                                       uint2 &out) {
+    const uint4 *tq = reinterpret_cast<const uint4 *>(tab);
+    const uint32_t nbm1 = (1u << (hbits - 1)) - 1;
+    uint32_t b = hslot(kk >> wbits, hbits - 1);
+    uint4 B = tq[b];
+    bool h0 = ((B.x & kmask) == kk) & (B.y != kEmptyPos);
+    bool h1 = ((B.z & kmask) == kk) & (B.w != kEmptyPos);
+    while (!(h0 | h1 | (B.w == kEmptyPos))) {      // full bucket without the key: next one
+        b = (b + 1) & nbm1;
+        B = tq[b];
+        h0 = ((B.x & kmask) == kk) & (B.y != kEmptyPos);
+        h1 = ((B.z & kmask) == kk) & (B.w != kEmptyPos);
+    }
+    out = h0 ? make_uint2(B.x, B.y) : make_uint2(B.z, B.w);
+    return h0 | h1;
+}
+
+// One partner-list entry e = (k, omega_jk) of partner j against the staged
+// chunk of owner r.  hit: k lies in the chunk (a hyper-triangle r, j, k);
+// mhit: its pattern is counted into the per-hyperedge counts.  Returns the
+// pattern when it is not the common-vertex one (counted in c9), else 0.
+template <bool PER_EDGE>
+__device__ __forceinline__ uint32_t probe_entry(const uint2 *tab, int hbits, int wbits, uint32_t wmask, uint32_t e,
+                                                const uint2 *ent_sm, const uint32_t *ent_mx, uint32_t *ent_ck,
+                                                const uint8_t *lut, int W, int si, int sj, int wij, bool fast_j,
+                                                uint32_t m0, uint32_t m1, uint32_t m2, uint32_t m3,
+                                                const GraphDesc &G, int32_t r, int32_t jr, uint32_t emask,
+                                                unsigned long long &c9, bool &hit, bool &mhit) {
+    uint2 sl;
+    if (!lookup(tab, e & ~wmask, ~wmask, wbits, hbits, sl)) return 0u;
+    hit = true;
+    const uint32_t pos = sl.y;
+    const int wik = (int)(sl.x & wmask);
+    const int wjk = (int)(e & wmask);
+    const uint2 sm = ent_sm[pos];
+    // Omega_rk = Omega_rj and all three omegas equal: the triple shares
+    // exactly those vertices and nothing else
+    const bool fast = fast_j & (wik == wij) & (wjk == wij) & (sm.y == m0) & ((int)sm.x > wij);
+    uint32_t p = kPatternCommonVertex, other = 0u;
+    if (!fast) {
+        const uint32_t k = e >> wbits;
+        int g;
+        if (W > 0) {
+            g = __popc(m0 & sm.y);
+            if (W > 1) {
+                const uint32_t *mx = ent_mx + pos * (kMaskWordsMax - 1);
+                g += __popc(m1 & mx[0]);
+                if (W > 2) g += __popc(m2 & mx[1]);
+                if (W > 3) g += __popc(m3 & mx[2]);
+            }
+        } else {
+            g = triple_common(G.eptr, G.emem, r, jr, (int32_t)k);
+        }
+        const uint32_t m7 = region_mask(si, sj, (int)sm.x, wij, wik, wjk, g);
+        if (m7 != kMaskCommonVertex) {
+            p = lut[m7];
+            other = p;
+        }
+    }
+    c9 += (other == 0u);
+    if (PER_EDGE && ((emask >> p) & 1u)) {
+        mhit = true;
+        atomicAdd(&ent_ck[pos], 1u);
+    }
+    return other;
+}
+
+// Add the wave's other-pattern hits (po[u] != 0) into lane p's counter.
+__device__ __forceinline__ void aggregate_other(const uint32_t *po, int lane, unsigned long long &wcnt) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; u++) {
+        uint64_t pend = __ballot(po[u] != 0);
+        while (pend) {
+            const int srcl = __ffsll((unsigned long long)pend) - 1;
+            const uint32_t p0 = (uint32_t)__shfl((int)po[u], srcl, kWave);
+            const uint64_t mm = __ballot(po[u] == p0);
+            if ((uint32_t)lane == p0) wcnt += (unsigned long long)__popcll(mm);
+            pend &= ~mm;
+        }
+    }
 }
 
 template <int CAP, int JP, bool PER_EDGE, bool PER_WEDGE>
-__global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
+__global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
     static_assert(JP <= kBlock, "one thread per partner");
-    constexpr int HMAX = 2 * CAP;
-    __shared__ uint64_t tab[HMAX];
-    __shared__ uint32_t ent_size[CAP];
-    __shared__ uint32_t ent_mask[CAP * kMaskWordsMax];
+    constexpr int HMAX = 4 * CAP;
+    __shared__ __align__(16) uint2 tab[HMAX];        // slots (entry, position); buckets of two
+    __shared__ uint2 ent_sm[CAP];                         // (|e_k|, Omega_rk word 0)
+    __shared__ uint32_t ent_mx[CAP * (kMaskWordsMax - 1)];  // Omega_rk words 1..3
     __shared__ uint32_t ent_ck[PER_EDGE ? CAP : 1];
     __shared__ int64_t seg_pre[kBlock + 1];
     __shared__ int64_t seg_src[JP];
@@ -99,8 +208,10 @@ __global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
 
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
+    const int wave = tid / kWave;
     if (tid < 128) lut[tid] = A.lut[tid];
-    unsigned long long wcnt = 0;     // lane p: this wave's count of pattern p
+    unsigned long long wcnt = 0;     // lane p: this wave's count of pattern p (p != 9)
+    unsigned long long c9 = 0;       // this lane's count of the common-vertex pattern
     unsigned long long all_probes = 0;
     int cur_g = -1;
 
@@ -115,64 +226,63 @@ __global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
         if (it < 0) break;
         const Item item = A.items[it];
         if (item.g != cur_g) {
-            if (cur_g >= 0) flush_wave_counts(wcnt, A.counts, cur_g, lane);
+            if (cur_g >= 0) flush_wave_counts(wcnt, c9, A.counts, cur_g, lane);
             cur_g = item.g;
         }
         const GraphDesc G = A.graphs[item.g];
         const uint32_t wmask = (1u << G.wbits) - 1;
+        const int wbits = G.wbits;
         const int32_t r = item.r;
-        const int64_t base = G.fptr[r];
-        const int32_t d = (int32_t)(G.fptr[r + 1] - base);
+        const int64_t base = gld(G.fptr + r);
+        const int32_t d = (int32_t)(gld(G.fptr + r + 1) - base);
         const bool single = item.cb == 0 && item.ce == d && item.jb == 0 && item.je == d - 1;
-        const int si = G.esize[r];
+        const int si = gld(G.esize + r);
         const int W = mask_words(si);
-        const int64_t mbase = G.mptr[r];
+        const int64_t mbase = gld(G.mptr + r);
         const int cl = item.ce - item.cb;
         int hbits = 6;
-        while ((1 << hbits) < 2 * cl) hbits++;
+        while ((1 << hbits) < 4 * cl) hbits++;
         const int H = 1 << hbits;
-        const uint32_t lo = G.fadj[base + item.cb] >> G.wbits;
-        const uint32_t hi = G.fadj[base + item.ce - 1] >> G.wbits;
+        const uint32_t lo = gld(G.fadj + base + item.cb) >> wbits;
+        const uint32_t hi = gld(G.fadj + base + item.ce - 1) >> wbits;
 
-        for (int s = tid; s < H; s += kBlock) tab[s] = kEmpty;
+        for (int s = tid; s < H; s += kBlock) tab[s] = make_uint2(0xFFFFFFFFu, kEmptyPos);
         __syncthreads();
         // stage the chunk
         for (int q = tid; q < cl; q += kBlock) {
-            uint32_t ent = G.fadj[base + item.cb + q];
-            uint32_t k = ent >> G.wbits;
-            ent_size[q] = (uint32_t)G.esize[k];
-            for (int w = 0; w < W; w++)
-                ent_mask[q * kMaskWordsMax + w] = G.fmask[mbase + (int64_t)(item.cb + q) * W + w];
+            const uint32_t ent = gld(G.fadj + base + item.cb + q);
+            const uint32_t k = ent >> wbits;
+            const int64_t mo = mbase + (int64_t)(item.cb + q) * W;
+            ent_sm[q] = make_uint2((uint32_t)gld(G.esize + k), W > 0 ? gld(G.fmask + mo) : 0u);
+            for (int w = 1; w < W; w++) ent_mx[q * (kMaskWordsMax - 1) + (w - 1)] = gld(G.fmask + mo + w);
             if (PER_EDGE) ent_ck[q] = 0;
-            uint64_t v = ((uint64_t)q << 32) | ent;
-            uint32_t slot = hslot(k, hbits);
-            while (atomicCAS((unsigned long long *)&tab[slot], (unsigned long long)kEmpty,
-                             (unsigned long long)v) != kEmpty)
-                slot = (slot + 1) & (H - 1);
+            // slot = (entry, position): claim the position word, then write the entry
+            uint32_t slot = hslot(k, hbits - 1) * 2;
+            while (atomicCAS(&tab[slot].y, kEmptyPos, (uint32_t)q) != kEmptyPos) slot = (slot + 1) & (H - 1);
+            tab[slot].x = ent;
         }
         // partner segments: N+(j) cut to the chunk's rank range
         const int nseg = item.je - item.jb;
         int64_t len = 0;
         if (tid < nseg) {
             const int pj = item.jb + tid;
-            const uint32_t jent = G.fadj[base + pj];
-            const uint32_t j = jent >> G.wbits;
-            int64_t a = G.fptr[j], b = G.fptr[j + 1];
+            const uint32_t jent = gld(G.fadj + base + pj);
+            const uint32_t j = jent >> wbits;
+            int64_t a = gld(G.fptr + j), b = gld(G.fptr + j + 1);
             if (!single) {
-                a = lower_rank(G.fadj, a, b, lo, G.wbits);
-                b = lower_rank(G.fadj, a, b, hi + 1, G.wbits);
+                a = lower_rank(G.fadj, a, b, lo, wbits);
+                b = lower_rank(G.fadj, a, b, hi + 1, wbits);
             }
             len = b - a;
             seg_src[tid] = a;
-            seg_size[tid] = (uint32_t)G.esize[j];
+            seg_size[tid] = (uint32_t)gld(G.esize + j);
             seg_om[tid] = jent & wmask;
-            for (int w = 0; w < W; w++) seg_mask[tid * kMaskWordsMax + w] = G.fmask[mbase + (int64_t)pj * W + w];
+            for (int w = 0; w < W; w++) seg_mask[tid * kMaskWordsMax + w] = gld(G.fmask + mbase + (int64_t)pj * W + w);
             if (PER_WEDGE) seg_cj[tid] = 0;
             if (PER_EDGE) seg_cjm[tid] = 0;
         }
         // exclusive scan of segment lengths
         {
-            const int wave = tid / kWave;
             int64_t incl = len;
 #pragma unroll
             for (int o = 1; o < kWave; o <<= 1) {
@@ -198,84 +308,188 @@ __global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
         const int64_t total = seg_pre[kBlock];
         all_probes += (unsigned long long)total;
 
-        // stream the partner lists through the hash
-        int q = -1;
-        int sj = 0, wij = 0;
-        uint32_t mj[kMaskWordsMax] = {0, 0, 0, 0};
-        int64_t src = 0;
-        uint32_t cj = 0, cjm = 0;
-        int32_t jrank = 0;
-        // wave-uniform loop: lane l of the wave takes entry fb + l
-        for (int64_t fb = tid - lane; fb < total; fb += kBlock) {
-            const int64_t f = fb + lane;
-            const bool valid = f < total;
-            bool hit = false;
-            uint32_t p = 0;
-            if (valid) {
-                if (q < 0 || seg_pre[q + 1] <= f) {
-                    if (q >= 0) {
-                        if (PER_WEDGE && cj) atomicAdd(&seg_cj[q], cj);
-                        if (PER_EDGE && cjm) atomicAdd(&seg_cjm[q], cjm);
-                    }
-                    cj = cjm = 0;
-                    int lo_s = q < 0 ? 0 : q + 1, hi_s = nseg;
-                    while (lo_s < hi_s) {
-                        int mid = (lo_s + hi_s) >> 1;
-                        if (seg_pre[mid + 1] <= f) lo_s = mid + 1; else hi_s = mid;
-                    }
-                    q = lo_s;
-                    sj = (int)seg_size[q];
-                    wij = (int)seg_om[q];
+        // Partner-list entries go through probe_entry(); both loops below
+        // keep the next tile's loads in flight while the current tile is
+        // classified.
+        if (total >= (int64_t)nseg * 64) {
+            // Dense items (long partner segments): one wave per partner, the
+            // partner's data wave-uniform, lanes striding over its segment.
+            constexpr int TILE = kWave * kUnroll;
+            int qd = wave;
+            while (qd < nseg && seg_pre[qd + 1] == seg_pre[qd]) qd += kBlock / kWave;
+            int64_t i0 = 0;
+            uint32_t entA[kUnroll];
+            bool valA[kUnroll];
+            if (qd < nseg) {
+                const int64_t slen = seg_pre[qd + 1] - seg_pre[qd];
+                const int64_t sbase = seg_src[qd];
 #pragma unroll
-                    for (int w = 0; w < kMaskWordsMax; w++) mj[w] = w < W ? seg_mask[q * kMaskWordsMax + w] : 0u;
-                    src = seg_src[q] - seg_pre[q];
-                    if (W == 0) jrank = (int32_t)(G.fadj[base + item.jb + q] >> G.wbits);
-                }
-                const uint32_t ent = G.fadj[src + f];
-                const uint32_t k = ent >> G.wbits;
-                uint32_t slot = hslot(k, hbits);
-                uint64_t v;
-                for (;;) {
-                    v = tab[slot];
-                    if (v == kEmpty || ((uint32_t)v >> G.wbits) == k) break;
-                    slot = (slot + 1) & (H - 1);
-                }
-                if (v != kEmpty) {
-                    const uint32_t pos = (uint32_t)(v >> 32);
-                    const int wik = (int)((uint32_t)v & wmask);
-                    const int wjk = (int)(ent & wmask);
-                    const int sk = (int)ent_size[pos];
-                    int g;
-                    if (W > 0) {
-                        g = 0;
-#pragma unroll
-                        for (int w = 0; w < kMaskWordsMax; w++)
-                            if (w < W) g += __popc(mj[w] & ent_mask[pos * kMaskWordsMax + w]);
-                    } else {
-                        g = triple_common(G.eptr, G.emem, r, jrank, (int32_t)k);
-                    }
-                    p = lut[region_mask(si, sj, sk, wij, wik, wjk, g)];
-                    hit = true;
-                    cj++;
-                    if (PER_EDGE && ((A.emask >> p) & 1u)) {
-                        cjm++;
-                        atomicAdd(&ent_ck[pos], 1u);
-                    }
+                for (int u = 0; u < kUnroll; u++) {
+                    const int64_t i = u * kWave + lane;
+                    valA[u] = i < slen;
+                    entA[u] = valA[u] ? gld(G.fadj + sbase + i) : 0u;
                 }
             }
-            // aggregate the wave's hits by pattern into lane p
-            uint64_t pend = __ballot(hit);
-            while (pend) {
-                const int srcl = __ffsll((unsigned long long)pend) - 1;
-                const uint32_t p0 = (uint32_t)__shfl((int)p, srcl, kWave);
-                const uint64_t mm = __ballot(hit && p == p0);
-                if ((uint32_t)lane == p0) wcnt += (unsigned long long)__popcll(mm);
-                pend &= ~mm;
+            unsigned long long hits = 0, mhits = 0;     // wave-uniform, current segment
+            while (qd < nseg) {
+                // the tile after this one
+                const int64_t slen = seg_pre[qd + 1] - seg_pre[qd];
+                int qn = qd;
+                int64_t in = i0 + TILE;
+                if (in >= slen) {
+                    qn = qd + kBlock / kWave;
+                    while (qn < nseg && seg_pre[qn + 1] == seg_pre[qn]) qn += kBlock / kWave;
+                    in = 0;
+                }
+                uint32_t entB[kUnroll];
+                bool valB[kUnroll];
+                if (qn < nseg) {
+                    const int64_t nlen = seg_pre[qn + 1] - seg_pre[qn];
+                    const int64_t nbase = seg_src[qn];
+#pragma unroll
+                    for (int u = 0; u < kUnroll; u++) {
+                        const int64_t i = in + u * kWave + lane;
+                        valB[u] = i < nlen;
+                        entB[u] = valB[u] ? gld(G.fadj + nbase + i) : 0u;
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < kUnroll; u++) {
+                        valB[u] = false;
+                        entB[u] = 0u;
+                    }
+                }
+                // this tile
+                const int sjd = __builtin_amdgcn_readfirstlane((int)seg_size[qd]);
+                const int wd = __builtin_amdgcn_readfirstlane((int)seg_om[qd]);
+                const uint32_t m0 = W > 0 ? (uint32_t)__builtin_amdgcn_readfirstlane((int)seg_mask[qd * kMaskWordsMax]) : 0u;
+                const uint32_t m1 = W > 1 ? seg_mask[qd * kMaskWordsMax + 1] : 0u;
+                const uint32_t m2 = W > 2 ? seg_mask[qd * kMaskWordsMax + 2] : 0u;
+                const uint32_t m3 = W > 3 ? seg_mask[qd * kMaskWordsMax + 3] : 0u;
+                const bool fastd = (W == 1) && (si > wd) && (sjd > wd);
+                const int32_t jr = (W == 0) ? (int32_t)(gld(G.fadj + base + item.jb + qd) >> wbits) : 0;
+                uint32_t po[kUnroll];
+                bool other = false;
+#pragma unroll
+                for (int u = 0; u < kUnroll; u++) {
+                    bool hit = false, mhit = false;
+                    po[u] = valA[u] ? probe_entry<PER_EDGE>(tab, hbits, wbits, wmask, entA[u], ent_sm, ent_mx, ent_ck,
+                                                            lut, W, si, sjd, wd, fastd, m0, m1, m2, m3, G, r, jr,
+                                                            A.emask, c9, hit, mhit)
+                                    : 0u;
+                    other |= po[u] != 0;
+                    if (PER_WEDGE) hits += (unsigned long long)__popcll(__ballot(hit));
+                    if (PER_EDGE) mhits += (unsigned long long)__popcll(__ballot(mhit));
+                }
+                if (__ballot(other)) aggregate_other(po, lane, wcnt);
+                if (qn != qd) {
+                    if (lane == 0) {
+                        if (PER_WEDGE) seg_cj[qd] = (uint32_t)hits;
+                        if (PER_EDGE) seg_cjm[qd] = (uint32_t)mhits;
+                    }
+                    hits = mhits = 0;
+                }
+                qd = qn;
+                i0 = in;
+#pragma unroll
+                for (int u = 0; u < kUnroll; u++) {
+                    entA[u] = entB[u];
+                    valA[u] = valB[u];
+                }
             }
-        }
-        if (q >= 0) {
-            if (PER_WEDGE && cj) atomicAdd(&seg_cj[q], cj);
-            if (PER_EDGE && cjm) atomicAdd(&seg_cjm[q], cjm);
+        } else {
+            // Flattened items: the partner segments laid end to end; each step
+            // a wave takes 64*kUnroll consecutive entries, kUnroll per lane.
+            int qa = -1;                   // address cursor
+            int64_t qa_end = 0, srca = 0;
+            int q = -1;                    // processing cursor
+            int sj = 0, wij = 0;
+            uint32_t mj0 = 0, mj1 = 0, mj2 = 0, mj3 = 0;
+            bool fast_j = false;
+            uint32_t cj = 0, cjm = 0;
+            int32_t jrank = 0;
+            const int64_t stride = (int64_t)kBlock * kUnroll;
+            auto fetch = [&](int64_t f0, uint32_t *ent, int *segu) {
+#pragma unroll
+                for (int u = 0; u < kUnroll; u++) {
+                    const int64_t f = f0 + u;
+                    segu[u] = -1;
+                    int64_t addr = 0;
+                    if (f < total) {
+                        if (f >= qa_end) {
+                            int lo_s = qa < 0 ? 0 : qa + 1, hi_s = nseg;
+                            while (lo_s < hi_s) {
+                                int mid = (lo_s + hi_s) >> 1;
+                                if (seg_pre[mid + 1] <= f) lo_s = mid + 1; else hi_s = mid;
+                            }
+                            qa = lo_s;
+                            qa_end = seg_pre[qa + 1];
+                            srca = seg_src[qa] - seg_pre[qa];
+                        }
+                        segu[u] = qa;
+                        addr = srca + f;
+                    }
+                    ent[u] = segu[u] >= 0 ? gld(G.fadj + addr) : 0u;
+                }
+            };
+            int64_t fb = (int64_t)wave * kWave * kUnroll;
+            uint32_t entA[kUnroll];
+            int seguA[kUnroll];
+            if (fb < total) fetch(fb + (int64_t)lane * kUnroll, entA, seguA);
+            for (; fb < total; fb += stride) {
+                uint32_t entB[kUnroll];
+                int seguB[kUnroll];
+                const int64_t fbn = fb + stride;
+                if (fbn < total) {
+                    fetch(fbn + (int64_t)lane * kUnroll, entB, seguB);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < kUnroll; u++) {
+                        entB[u] = 0u;
+                        seguB[u] = -1;
+                    }
+                }
+                uint32_t po[kUnroll];
+                bool other = false;
+#pragma unroll
+                for (int u = 0; u < kUnroll; u++) {
+                    po[u] = 0;
+                    if (seguA[u] < 0) continue;
+                    if (seguA[u] != q) {
+                        if (q >= 0) {
+                            if (PER_WEDGE && cj) atomicAdd(&seg_cj[q], cj);
+                            if (PER_EDGE && cjm) atomicAdd(&seg_cjm[q], cjm);
+                        }
+                        cj = cjm = 0;
+                        q = seguA[u];
+                        sj = (int)seg_size[q];
+                        wij = (int)seg_om[q];
+                        fast_j = (W == 1) && (si > wij) && (sj > wij);
+                        mj0 = W > 0 ? seg_mask[q * kMaskWordsMax + 0] : 0u;
+                        mj1 = W > 1 ? seg_mask[q * kMaskWordsMax + 1] : 0u;
+                        mj2 = W > 2 ? seg_mask[q * kMaskWordsMax + 2] : 0u;
+                        mj3 = W > 3 ? seg_mask[q * kMaskWordsMax + 3] : 0u;
+                        if (W == 0) jrank = (int32_t)(gld(G.fadj + base + item.jb + q) >> wbits);
+                    }
+                    bool hit = false, mhit = false;
+                    po[u] = probe_entry<PER_EDGE>(tab, hbits, wbits, wmask, entA[u], ent_sm, ent_mx, ent_ck, lut, W,
+                                                  si, sj, wij, fast_j, mj0, mj1, mj2, mj3, G, r, jrank, A.emask, c9,
+                                                  hit, mhit);
+                    other |= po[u] != 0;
+                    cj += hit;
+                    cjm += mhit;
+                }
+                if (__ballot(other)) aggregate_other(po, lane, wcnt);
+#pragma unroll
+                for (int u = 0; u < kUnroll; u++) {
+                    entA[u] = entB[u];
+                    seguA[u] = seguB[u];
+                }
+            }
+            if (q >= 0) {
+                if (PER_WEDGE && cj) atomicAdd(&seg_cj[q], cj);
+                if (PER_EDGE && cjm) atomicAdd(&seg_cjm[q], cjm);
+            }
         }
         __syncthreads();
         // per-wedge counters (single-graph launches only)
@@ -299,7 +513,7 @@ __global__ __launch_bounds__(kBlock) void k_close(CloseArgs A) {
             }
         }
     }
-    if (cur_g >= 0) flush_wave_counts(wcnt, A.counts, cur_g, lane);
+    if (cur_g >= 0) flush_wave_counts(wcnt, c9, A.counts, cur_g, lane);
     if (tid == 0 && all_probes) atomicAdd(A.probes, all_probes);
 }
 

@@ -73,6 +73,12 @@ def load_library() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
                           "(python -m paper_2504_02271_amd.build) first")
+    # torch supplies device memory and streams; load its HIP runtime first so
+    # that the library binds to the same one
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     sig = {
         "htri_graph_load": ([_P, _i64, _P, _i32, _u32, _P, _P, ctypes.POINTER(_P)], ctypes.c_int),
@@ -141,16 +147,22 @@ class TorchMemory:
         import torch
         self.torch = torch
         self.device = device
+        alloc_fn = torch.cuda.caching_allocator_alloc
+        delete_fn = torch.cuda.caching_allocator_delete
 
         def _alloc(nbytes, stream, ctx):
             try:
-                return self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device, stream)
+                return alloc_fn(int(nbytes), device, stream)
             except Exception:
                 return None
 
         def _free(ptr, stream, ctx):
-            if ptr:
-                self.torch.cuda.caching_allocator_delete(ptr)
+            # may run during interpreter shutdown, after torch is torn down
+            try:
+                if ptr:
+                    delete_fn(ptr)
+            except Exception:
+                pass
 
         self._alloc_cb = ALLOC_FN(_alloc)
         self._free_cb = FREE_FN(_free)
