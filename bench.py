@@ -51,6 +51,72 @@ def closure_bytes(summary, cstats):
     return 4 * S + 8 * nw + 4 * mask_words + 8 * nw
 
 
+def closure_source_sha() -> str:
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2504_02271_amd", "csrc", "closure.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per closure launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when
+    there is none for this workload or the kernel source has changed since."""
+    path = os.path.join(ROOT, "profiles", f"k_close_{workload}_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("closure.hip sha256") != closure_source_sha():
+        return None
+    try:
+        return float(vals["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def estimator_study(seeds: int, log_fn):
+    """Learned vs uniform hyperwedge sampling at equal GPU time on the
+    tags-shaped evaluation graph (seed 5); the proposal network is trained
+    on 20 co-authorship-shaped graphs (seeds 100..119), never on the
+    evaluation graph."""
+    import torch
+    from paper_2504_02271_amd import htri, learn, synth
+    t0 = time.time()
+    train = [synth.generate(sp) for sp in synth.training_specs(20)]
+    X, y = learn.training_rows(train, rows_per_graph=200_000, top_rows=50_000, seed=0, target="importance")
+    del train
+    model = learn.train_proposal(X, y, steps=3000, batch=4096, lr=2e-3, seed=0)
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    log_fn(f"[bench] proposal trained on {X.shape[0]} rows in {train_s:.1f} s")
+    del X, y
+    ev = synth.generate(synth.config("tags_eval"))
+    G = htri.graph_load(ev.offsets, ev.members, ev.num_vertices)
+    G.build_wedges()
+    exact, _, _ = G.count_patterns()
+    rows = learn.equal_time_study(G, exact, model, budgets=(0.001, 0.01, 0.05), seeds=seeds,
+                                  log=log_fn)
+    for r in rows:
+        r["learned_wins"] = r["learned_rel_err"] < r["uniform_rel_err"]
+    return {
+        "eval_workload": "tags-shaped evaluation graph: as the exact workload with seed 5 "
+                         f"({G.num_wedges} hyperwedges)",
+        "exact_counts": [int(x) for x in exact],
+        "proposal": "16-64-64-1 ReLU network trained on the GPU (3000 Adam steps, target log1p of the "
+                    "per-pattern-normalised closure importance) on 20 co-authorship-shaped graphs, seeds 100-119",
+        "proposal_training_s": train_s,
+        "seeds": seeds,
+        "defensive_mix": 0.1,
+        "error": "mean over patterns with H_p > 0 of |est_p - H_p| / H_p, averaged over seeds",
+        "time": "device time of the whole estimate (pool, scoring, scan, draws, closure, reduce), hipEvents",
+        "budgets": rows,
+    }
+
+
 def cpu_baseline(g, seconds: float, seed: int = 11):
     """The CPU oracle (plain two-step count from the vertex lists) on a random
     sample of owners of the same hypergraph, timed on the host cores."""
@@ -92,6 +158,8 @@ def main() -> int:
     ap.add_argument("--workload", default="tags", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-study", action="store_true", help="skip the learned-vs-uniform estimator study")
+    ap.add_argument("--study-seeds", type=int, default=32)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -168,6 +236,12 @@ def main() -> int:
         cpu = cpu_baseline(g, args.cpu_seconds)
         log(f"[bench] CPU oracle: {cpu['value']:.3e} hyperwedges/s")
 
+    study = None
+    if not args.no_study:
+        log("[bench] learned vs uniform estimator at equal GPU time ...")
+        study = estimator_study(args.study_seeds, log)
+
+    traffic = measured_traffic(args.workload)
     out = {
         "metric": METRIC,
         "value": value,
@@ -199,12 +273,13 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
             "algorithmic_bytes": B,
             "closure_stream_S": int(cstats[0]),
             "entries_probed": int(cstats[1]),
         },
         "cpu_baseline": cpu,
+        "estimator": study,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -17,29 +17,65 @@ import numpy as np
 from . import htri
 
 
-def training_rows(graphs: Iterable, rows_per_graph: int = 200_000, seed: int = 0):
-    """(X float32 [N,16], y float32 [N]) on the GPU: features and log1p of the
-    exact forward closure count of hyperwedges drawn uniformly from each graph."""
+def wedge_importance(G, H: np.ndarray, chunk: int = 1 << 21) -> np.ndarray:
+    """Per-hyperwedge importance u(w) = sqrt(sum_p (c_p(w) |W| / H_p)^2) / n_p
+    over the n_p patterns with H_p > 0, where c_p(w) is the forward closure of
+    w that falls in pattern p.  A proposal q(w) proportional to u(w) minimises
+    sum_p Var(H_p estimate) / H_p^2, the squared form of the per-pattern
+    relative error averaged over patterns (the accuracy measure of the
+    experiments on approximate counting).  float64 [|W|] on the host."""
+    nw = G.num_wedges
+    Hp = np.asarray(H, np.float64)[1:]
+    live = Hp > 0
+    out = np.zeros(nw, np.float64)
+    if nw == 0 or not live.any():
+        return out
+    scale = np.where(live, nw / np.where(live, Hp, 1.0), 0.0)
+    for a in range(0, nw, chunk):
+        b = min(nw, a + chunk)
+        c = G.close_wedges(np.arange(a, b, dtype=np.int64))[:, 1:].astype(np.float64)
+        out[a:b] = np.sqrt(((c * scale) ** 2).sum(axis=1)) / live.sum()
+    return out
+
+
+def training_rows(graphs: Iterable, rows_per_graph: int = 200_000, top_rows: int = 50_000, seed: int = 0,
+                  target: str = "importance"):
+    """(X float32 [N,16], y float32 [N]) on the GPU for the proposal network.
+
+    target "importance": y = log1p(u(w)) of wedge_importance, rows = a
+    uniform sample of each graph's hyperwedges plus its top_rows most
+    important ones (the wedges that carry the rare patterns are too few for
+    a uniform sample to show them).  target "closure": y = log1p of the
+    exact forward closure count, uniform rows only."""
     import torch
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(seed)
+    rng = np.random.default_rng(seed)
     xs, ys = [], []
     for g in graphs:
         G = htri.graph_load(g.offsets, g.members, g.num_vertices)
         G.build_wedges()
-        _, _, pw = G.count_patterns(per_wedge=True, device_out=True)
-        X = G.wedge_features()
-        n = X.shape[0]
+        n = G.num_wedges
         if n == 0:
+            G.close()
             continue
-        if n > rows_per_graph:
-            idx = torch.randint(0, n, (rows_per_graph,), device="cuda", generator=gen)
-            X = X[idx]
-            c = pw[idx]
+        if target == "closure":
+            _, _, pw = G.count_patterns(per_wedge=True, device_out=True)
+            idx = np.sort(rng.choice(n, size=min(n, rows_per_graph), replace=False))
+            idt = torch.from_numpy(idx).cuda()
+            y = torch.log1p(pw[idt].to(torch.float32))
+        elif target == "importance":
+            H, _, _ = G.count_patterns()
+            u = wedge_importance(G, H)
+            uni = rng.choice(n, size=min(n, rows_per_graph), replace=False)
+            top = np.argpartition(u, -min(n, top_rows))[-min(n, top_rows):]
+            idx = np.unique(np.concatenate([uni, top]))
+            idt = torch.from_numpy(idx).cuda()
+            y = torch.from_numpy(np.log1p(u[idx]).astype(np.float32)).cuda()
         else:
-            c = pw
-        xs.append(X.contiguous())
-        ys.append(torch.log1p(c.to(torch.float32)))
+            raise ValueError(f"unknown target {target!r}")
+        X = G.wedge_features()
+        xs.append(X[idt].contiguous())
+        ys.append(y)
+        del X
         G.close()
     return torch.cat(xs).contiguous(), torch.cat(ys).contiguous()
 
@@ -73,22 +109,38 @@ def _run(G, proposal, n, seed, model, mix, pool_factor):
                       pool_factor=pool_factor)
 
 
+POOL_FACTOR = 16.0
+FULL_SCORING_FRACTION = 0.1
+
+
+def pool_factor_for(n: int, nw: int, pool_factor: float = POOL_FACTOR,
+                    full_fraction: float = FULL_SCORING_FRACTION) -> float:
+    """Candidate source of the learned sampler for n draws out of nw
+    hyperwedges: a uniform pool of pool_factor * n candidates while that pool
+    covers less than full_fraction of the wedges, else every wedge scored
+    (pool factor 0).  Scoring all wedges has a fixed cost that only pays off
+    once the pool would be a sizeable part of the graph anyway."""
+    return pool_factor if pool_factor * n < full_fraction * nw else 0.0
+
+
 def equal_time_study(G, exact: np.ndarray, model, budgets: Sequence[float] = (0.001, 0.01, 0.05),
-                     seeds: int = 32, mix: float = 0.1, pool_factor: float = 16.0,
+                     seeds: int = 32, mix: float = 0.1, pool_factor="auto",
                      log=print) -> List[Dict]:
     """Learned vs uniform hyperwedge sampling at equal GPU time.  For each
     budget b: the learned sampler draws b*|wedges| samples (from a uniform pool
-    of pool_factor times as many candidates); its device time sets the time
-    budget; the uniform sampler gets as many samples as fit in that time
+    of pool_factor times as many candidates, or from all wedges with pool
+    factor 0; "auto" picks with pool_factor_for); its device time sets the
+    time budget; the uniform sampler gets as many samples as fit in that time
     (calibrated to within 5%).  Errors over `seeds` independent runs."""
     nw = G.num_wedges
     out = []
     for b in budgets:
         nL = max(1, int(round(b * nw)))
-        _run(G, 1, nL, 10_000, model, mix, pool_factor)                 # warm-up
+        pf = pool_factor_for(nL, nw) if pool_factor == "auto" else float(pool_factor)
+        _run(G, 1, nL, 10_000, model, mix, pf)                 # warm-up
         rl, tl, el = [], [], []
         for s in range(seeds):
-            est, se, ms = _run(G, 1, nL, s, model, mix, pool_factor)
+            est, se, ms = _run(G, 1, nL, s, model, mix, pf)
             rl.append(relative_error(est, exact))
             tl.append(ms)
             el.append(est)
@@ -112,7 +164,7 @@ def equal_time_study(G, exact: np.ndarray, model, budgets: Sequence[float] = (0.
             pl = np.where(H > 0, np.abs(el - H).mean(axis=0) / H, np.nan)[1:]
             pu = np.where(H > 0, np.abs(eu - H).mean(axis=0) / H, np.nan)[1:]
         row = {
-            "budget": b, "learned_samples": nL, "uniform_samples": nU,
+            "budget": b, "learned_samples": nL, "uniform_samples": nU, "pool_factor": pf,
             "learned_ms": t_target, "uniform_ms": float(np.median(tu)),
             "learned_rel_err": float(np.mean(rl)), "uniform_rel_err": float(np.mean(ru)),
             "learned_total_rel_err": float(np.mean(np.abs(el[:, 0] - H[0]) / H[0])),

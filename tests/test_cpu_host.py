@@ -152,3 +152,68 @@ def test_generators_deterministic_and_shaped():
     specs = synth.batch_specs(512)
     es = np.array([s.num_edges for s in specs])
     assert len(specs) == 512 and es.min() >= 1000 and es.max() <= 200000
+
+
+class _OracleWedges:
+    """Stand-in for a loaded graph: per-pattern forward closures of every
+    hyperwedge from the oracle, in the order of the oracle's wedge list."""
+
+    def __init__(self, g):
+        from oracle import core
+        o = core.OracleGraph(g.offsets, g.members, g.num_vertices)
+        off, mem, _ = o.csr()
+        rank = core.prec_rank(off, mem, g.num_vertices)
+        wi, wj, _ = o.wedges()
+        lo, hi = sampling.prec_wedge_order(rank, wi, wj)
+        self.C = o.wedge_closure_ranked(rank, lo, hi)
+        self.H = o.count().H
+        self.num_wedges = lo.shape[0]
+
+    def close_wedges(self, idx):
+        return self.C[idx]
+
+
+def _pattern_variance(C, H, q):
+    """sum_p Var(c_p(w)/q(w)) / H_p^2 for one draw w ~ q (exact, by summation)."""
+    live = H[1:] > 0
+    c = C[:, 1:][:, live].astype(np.float64)
+    h = H[1:][live].astype(np.float64)
+    return float(((((c ** 2) / q[:, None]).sum(axis=0) - h ** 2) / h ** 2).sum())
+
+
+def test_wedge_importance_minimises_the_pattern_variance():
+    """The training target of the learned proposal: q proportional to
+    wedge_importance gives a smaller summed relative variance than uniform,
+    than q proportional to the total closure, and than perturbed versions
+    of itself (it is the minimiser, by Cauchy-Schwarz)."""
+    from paper_2504_02271_amd import learn
+    g = synth.random_small(5, 160, 30, 1, 6)
+    G = _OracleWedges(g)
+    u = learn.wedge_importance(G, G.H, chunk=97)
+    assert u.shape == (G.num_wedges,) and (u >= 0).all()
+    live = G.H[1:] > 0
+    assert np.array_equal(u > 0, (G.C[:, 1:][:, live] > 0).any(axis=1))
+    # one wedge's value from the definition
+    w = int(np.argmax(u))
+    want = np.sqrt(((G.C[w, 1:][live] * G.num_wedges / G.H[1:][live]) ** 2).sum()) / live.sum()
+    assert np.isclose(u[w], want, rtol=1e-12)
+    sup = u > 0
+    C, H = G.C[sup], G.H
+    q_opt = u[sup] / u[sup].sum()
+    v_opt = _pattern_variance(C, H, q_opt)
+    q_uni = np.full(sup.sum(), 1.0 / sup.sum())
+    tot = C[:, 0].astype(np.float64)
+    q_tot = (tot + 1e-12) / (tot + 1e-12).sum()
+    assert v_opt <= _pattern_variance(C, H, q_uni) + 1e-9
+    assert v_opt <= _pattern_variance(C, H, q_tot) + 1e-9
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        q = q_opt * np.exp(rng.normal(scale=0.3, size=q_opt.shape[0]))
+        q /= q.sum()
+        assert v_opt <= _pattern_variance(C, H, q) + 1e-9
+
+
+def test_pool_policy():
+    from paper_2504_02271_amd import learn
+    assert learn.pool_factor_for(1000, 10_000_000) == learn.POOL_FACTOR
+    assert learn.pool_factor_for(100_000, 10_000_000) == 0.0
