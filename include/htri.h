@@ -91,6 +91,10 @@ typedef struct {
 #define HTRI_INPUT_ON_DEVICE 2u   /* offsets/members are device pointers      */
 #define HTRI_OUTPUT_ON_DEVICE 4u  /* per_edge / per_wedge are device pointers */
 #define HTRI_ORDER_INPUT 8u       /* orient by normalised id, not by delta    */
+/* htri_count_patterns flags (with HTRI_OUTPUT_ON_DEVICE) */
+#define HTRI_COUNT_NO_WINDOW 16u     /* close every owner by probing           */
+#define HTRI_COUNT_WINDOW_ALWAYS 32u /* use the dense window whenever it holds */
+                                     /* a hyperwedge (else: when dense enough) */
 
 /* Load and normalise a hypergraph (Def. 2.1 and the distinct-hyperedge
  * assumption of Section 2), build E_v (Algorithm 2).
@@ -149,23 +153,34 @@ htri_status htri_get_wedges(const htri_graph *g, int32_t *src, int32_t *dst, int
  *   per_wedge   NULL or int32[|wedges|]: per hyperwedge (htri_get_wedges
  *               order), the number of third hyperedges that close it and
  *               come after dst in prec (all patterns).
- *   out_flags   0 or HTRI_OUTPUT_ON_DEVICE.
- * Errors: HTRI_E_STATE (no wedges yet), HTRI_E_OOM, HTRI_E_DEVICE. */
+ *   out_flags   HTRI_OUTPUT_ON_DEVICE, and at most one of
+ *               HTRI_COUNT_NO_WINDOW / HTRI_COUNT_WINDOW_ALWAYS.  By default
+ *               the owners of the top ranks (up to 16384 of them) are closed
+ *               by bitmap intersection when the hyperwedges among them are
+ *               dense (at least 1/16 of all pairs); the counts do not
+ *               depend on the choice.
+ * Errors: HTRI_E_STATE (no wedges yet), HTRI_E_INVALID (unknown flag),
+ * HTRI_E_OOM, HTRI_E_DEVICE. */
 htri_status htri_count_patterns(htri_graph *g, uint32_t per_edge_pattern_mask, int64_t counts[21],
                                 int64_t *per_edge, int32_t *per_wedge, uint32_t out_flags);
 
 /* Device time of the stages of the last htri_build_wedges +
  * htri_count_patterns, milliseconds: [0] wedge build, [1] schedule,
- * [2] closure kernel, [3] reduce.  Measured with HIP events on the
- * handle's stream. */
-htri_status htri_last_timings(const htri_graph *g, double ms[4]);
+ * [2] closure (window and probing), [3] reduce, [4] the dense window
+ * (bitmaps and their closure), [5] the probing closure kernel.  Measured
+ * with HIP events on the handle's stream. */
+htri_status htri_last_timings(const htri_graph *g, double ms[6]);
 
 /* Work census of the last htri_count_patterns: out[0] = S, the closure
- * stream sum over hyperwedges (r, j) of |N+(j)| (the entries the method must
- * examine); out[1] = entries the kernel actually probed (partner lists are
- * cut to each chunk's rank range); out[2] = work items; out[3] = 32-bit
- * Omega mask words stored; out[4] = closure blocks launched. */
-htri_status htri_closure_stats(const htri_graph *g, int64_t out[5]);
+ * stream sum over hyperwedges (r, j) of |N+(j)|; out[1] = entries the
+ * probing kernel probed (partner lists are cut to each chunk's rank range);
+ * out[2] = work items; out[3] = 32-bit Omega mask words stored; out[4] =
+ * closure blocks launched; out[5] = rows of the dense window (0: none);
+ * out[6] = hyperwedges owned inside it; out[7] = S over the owners outside
+ * it; out[8] = hyperwedges owned outside it; out[9] = mask words of those;
+ * out[10] = 32-bit bitmap words the window closure read; out[11] = window
+ * hits enumerated one by one (all but the bulk-counted common-vertex ones). */
+htri_status htri_closure_stats(const htri_graph *g, int64_t out[12]);
 
 /* ---------------------------------------------------------------- sampling */
 

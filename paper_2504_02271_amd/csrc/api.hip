@@ -156,9 +156,9 @@ htri_status htri_clear_wedges(htri_graph *h) {
     });
 }
 
-htri_status htri_closure_stats(const htri_graph *h, int64_t out[5]) {
+htri_status htri_closure_stats(const htri_graph *h, int64_t out[12]) {
     if (!h || !out) return HTRI_E_INVALID;
-    std::memcpy(out, h->g.cstats, sizeof(int64_t) * 5);
+    std::memcpy(out, h->g.cstats, sizeof(int64_t) * 12);
     return HTRI_OK;
 }
 
@@ -191,7 +191,8 @@ htri_status htri_get_wedges(const htri_graph *hc, int32_t *src, int32_t *dst, in
 htri_status htri_count_patterns(htri_graph *h, uint32_t per_edge_pattern_mask, int64_t counts[21],
                                 int64_t *per_edge, int32_t *per_wedge, uint32_t out_flags) {
     if (!h || !counts) return HTRI_E_INVALID;
-    if (out_flags & ~HTRI_OUTPUT_ON_DEVICE) return HTRI_E_INVALID;
+    if (out_flags & ~(HTRI_OUTPUT_ON_DEVICE | HTRI_COUNT_NO_WINDOW | HTRI_COUNT_WINDOW_ALWAYS)) return HTRI_E_INVALID;
+    if ((out_flags & HTRI_COUNT_NO_WINDOW) && (out_flags & HTRI_COUNT_WINDOW_ALWAYS)) return HTRI_E_INVALID;
     if (!h->g.have_wedges) {
         h->g.err = "htri_build_wedges has not run";
         return HTRI_E_STATE;
@@ -213,7 +214,7 @@ htri_status htri_count_patterns(htri_graph *h, uint32_t per_edge_pattern_mask, i
             else { cw_tmp.alloc(g.al, g.nw); cw_dev = cw_tmp.p; }
         }
         int64_t c[21];
-        htri::count_patterns(g, mask, c, t_dev, cw_dev);
+        htri::count_patterns(g, mask, out_flags, c, t_dev, cw_dev);
         if (per_edge && !dev && g.m)
             HTRI_HIP(hipMemcpyAsync(per_edge, t_dev, sizeof(int64_t) * g.m, hipMemcpyDeviceToHost, g.stream));
         if (per_wedge && !dev && g.nw)
@@ -223,12 +224,14 @@ htri_status htri_count_patterns(htri_graph *h, uint32_t per_edge_pattern_mask, i
     });
 }
 
-htri_status htri_last_timings(const htri_graph *h, double ms[4]) {
+htri_status htri_last_timings(const htri_graph *h, double ms[6]) {
     if (!h || !ms) return HTRI_E_INVALID;
     ms[0] = h->g.tm.wedges_ms;
     ms[1] = h->g.tm.schedule_ms;
     ms[2] = h->g.tm.closure_ms;
     ms[3] = h->g.tm.reduce_ms;
+    ms[4] = h->g.tm.window_ms;
+    ms[5] = h->g.tm.probe_ms;
     return HTRI_OK;
 }
 

@@ -28,8 +28,8 @@ __global__ void k_copy_items(const Item *src, int64_t n, Item *dst) {
 
 struct Plan {
     htri_schedule sched{};
-    DBuf<Item> items;
-    int64_t nitems = 0;
+    DBuf<Item> items, witems;            // block items, single-owner items
+    int64_t nitems = 0, nwitems = 0;
     int nblocks = 1;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -48,7 +48,7 @@ struct htri_batch {
     std::vector<std::unique_ptr<htri::Graph>> graphs;
     htri::DBuf<htri::GraphDesc> descs;
     htri::DBuf<uint8_t> lut;
-    htri::DBuf<unsigned long long> ctr;  // [0] queue, [1] probes, [2..] counts[g][21]
+    htri::DBuf<unsigned long long> ctr;  // [0] queue, [1] probes, [2..] counts[g][21], then the wave queue
     std::vector<std::unique_ptr<htri::Plan>> plans;
     std::string err;
     ~htri_batch() {
@@ -86,28 +86,36 @@ Plan &plan_for(htri_batch &B, const htri_schedule &sc) {
     if (sc.order == 1)
         std::stable_sort(ord.begin(), ord.end(),
                          [&](int a, int b) { return B.graphs[a]->nw < B.graphs[b]->nw; });
-    std::vector<DBuf<Item>> parts(n);
-    std::vector<int64_t> cnt(n, 0);
-    int64_t total = 0;
+    std::vector<ItemLists> parts(n);
+    int64_t total = 0, wtotal = 0;
     for (int q = 0; q < n; q++) {
         const int gi = ord[q];
-        cnt[q] = build_items(*B.graphs[gi], gi, cfg, parts[q]);
-        total += cnt[q];
+        build_items(*B.graphs[gi], gi, cfg, parts[q], B.graphs[gi]->m);
+        total += parts[q].nblock;
+        wtotal += parts[q].nwave;
     }
     plan->items.alloc(B.al, total);
-    int64_t off = 0;
+    plan->witems.alloc(B.al, wtotal);
+    int64_t off = 0, woff = 0;
     for (int q = 0; q < n; q++) {
-        if (cnt[q]) {
-            hipLaunchKernelGGL(k_copy_items, dim3(grid_for(cnt[q], 256, 4096)), dim3(256), 0, B.stream, parts[q].p,
-                               cnt[q], plan->items.p + off);
+        if (parts[q].nblock) {
+            hipLaunchKernelGGL(k_copy_items, dim3(grid_for(parts[q].nblock, 256, 4096)), dim3(256), 0, B.stream,
+                               parts[q].block.p, parts[q].nblock, plan->items.p + off);
             HTRI_LAUNCH_CHECK();
         }
-        off += cnt[q];
+        if (parts[q].nwave) {
+            hipLaunchKernelGGL(k_copy_items, dim3(grid_for(parts[q].nwave, 256, 4096)), dim3(256), 0, B.stream,
+                               parts[q].wave.p, parts[q].nwave, plan->witems.p + woff);
+            HTRI_LAUNCH_CHECK();
+        }
+        off += parts[q].nblock;
+        woff += parts[q].nwave;
     }
     HTRI_HIP(hipStreamSynchronize(B.stream));
     plan->nitems = total;
+    plan->nwitems = wtotal;
     plan->nblocks = device_cu_count() * close_blocks_per_cu(cfg, false, false);
-    if ((int64_t)plan->nblocks > total) plan->nblocks = (int)std::max<int64_t>(total, 1);
+    if ((int64_t)plan->nblocks > total + wtotal) plan->nblocks = (int)std::max<int64_t>(total + wtotal, 1);
     B.plans.push_back(std::move(plan));
     return *B.plans.back();
 }
@@ -117,6 +125,9 @@ CloseArgs batch_args(htri_batch &B, const Plan &P) {
     a.items = P.items.p;
     a.nitems = P.nitems;
     a.queue = (unsigned int *)B.ctr.p;
+    a.witems = P.witems.p;
+    a.nwitems = P.nwitems;
+    a.wqueue = (unsigned int *)(B.ctr.p + 2 + 21 * (int64_t)B.graphs.size());
     a.graphs = B.descs.p;
     a.emask = 0x1FFFFEu;
     a.lut = B.lut.p;
@@ -126,7 +137,7 @@ CloseArgs batch_args(htri_batch &B, const Plan &P) {
 }
 
 void enqueue_batch(htri_batch &B, const Plan &P) {
-    const int64_t nctr = 2 + 21 * (int64_t)B.graphs.size();
+    const int64_t nctr = 3 + 21 * (int64_t)B.graphs.size();
     hipLaunchKernelGGL(k_zero_u64, dim3(grid_for(nctr, 256, 1024)), dim3(256), 0, B.stream, B.ctr.p, nctr);
     HTRI_LAUNCH_CHECK();
     CloseConfig cfg;
@@ -230,7 +241,7 @@ htri_status htri_batch_load(int32_t count, const int64_t *const *edge_offsets, c
             HTRI_HIP(hipMemcpyAsync(B->descs.p, d.data(), sizeof(GraphDesc) * d.size(), hipMemcpyHostToDevice, B->stream));
         B->lut.alloc(B->al, 128);
         HTRI_HIP(hipMemcpyAsync(B->lut.p, pattern_lut(), 128, hipMemcpyHostToDevice, B->stream));
-        B->ctr.alloc(B->al, 2 + 21 * (size_t)count);
+        B->ctr.alloc(B->al, 3 + 21 * (size_t)count);
         HTRI_HIP(hipStreamSynchronize(B->stream));
     });
     if (st != HTRI_OK) {
@@ -292,16 +303,15 @@ htri_status htri_batch_count_per_graph(htri_batch *b, const htri_schedule *sched
         if (!valid_config(cfg)) fail(HTRI_E_INVALID, "schedule: chunk 256|512, partners 128|256");
         const int n = (int)b->graphs.size();
         // items of each graph (graph index 0 in its own one-graph launch)
-        std::vector<DBuf<Item>> items(n);
-        std::vector<int64_t> cnt(n);
+        std::vector<ItemLists> items(n);
         std::vector<DBuf<GraphDesc>> desc(n);
         for (int g = 0; g < n; g++) {
-            cnt[g] = build_items(*b->graphs[g], 0, cfg, items[g]);
+            build_items(*b->graphs[g], 0, cfg, items[g], b->graphs[g]->m);
             desc[g].alloc(b->al, 1);
             GraphDesc d = graph_desc(*b->graphs[g]);
             HTRI_HIP(hipMemcpyAsync(desc[g].p, &d, sizeof(d), hipMemcpyHostToDevice, b->stream));
         }
-        DBuf<unsigned long long> ctr(b->al, (size_t)n * 23);
+        DBuf<unsigned long long> ctr(b->al, (size_t)n * 24);   // per graph: queue, probes, counts[21], wave queue
         HTRI_HIP(hipStreamSynchronize(b->stream));
         const int per_cu = close_blocks_per_cu(cfg, false, false);
         hipEvent_t e0, e1;
@@ -309,20 +319,24 @@ htri_status htri_batch_count_per_graph(htri_batch *b, const htri_schedule *sched
         HTRI_HIP(hipEventCreate(&e1));
         HTRI_HIP(hipEventRecord(e0, b->stream));
         for (int g = 0; g < n; g++) {
-            unsigned long long *c = ctr.p + 23 * (int64_t)g;
-            hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, b->stream, c, (int64_t)23);
+            unsigned long long *c = ctr.p + 24 * (int64_t)g;
+            hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, b->stream, c, (int64_t)24);
             HTRI_LAUNCH_CHECK();
             CloseArgs a{};
-            a.items = items[g].p;
-            a.nitems = cnt[g];
+            a.items = items[g].block.p;
+            a.nitems = items[g].nblock;
             a.queue = (unsigned int *)c;
+            a.witems = items[g].wave.p;
+            a.nwitems = items[g].nwave;
+            a.wqueue = (unsigned int *)(c + 23);
             a.graphs = desc[g].p;
             a.emask = 0x1FFFFEu;
             a.lut = b->lut.p;
             a.counts = c + 2;
             a.probes = c + 1;
             int nb = device_cu_count() * per_cu;
-            if ((int64_t)nb > cnt[g]) nb = (int)std::max<int64_t>(cnt[g], 1);
+            const int64_t ni = items[g].nblock + items[g].nwave;
+            if ((int64_t)nb > ni) nb = (int)std::max<int64_t>(ni, 1);
             launch_close_kernel(cfg, false, false, a, nb, b->stream);
         }
         HTRI_HIP(hipEventRecord(e1, b->stream));
@@ -331,12 +345,12 @@ htri_status htri_batch_count_per_graph(htri_batch *b, const htri_schedule *sched
         HTRI_HIP(hipEventElapsedTime(&ms, e0, e1));
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        std::vector<unsigned long long> h((size_t)n * 23);
+        std::vector<unsigned long long> h((size_t)n * 24);
         HTRI_HIP(hipMemcpy(h.data(), ctr.p, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost));
         for (int g = 0; g < n; g++) {
             int64_t tot = 0;
             for (int p = 1; p <= 20; p++) {
-                counts[g * 21 + p] = (int64_t)h[23 * (size_t)g + 2 + p];
+                counts[g * 21 + p] = (int64_t)h[24 * (size_t)g + 2 + p];
                 tot += counts[g * 21 + p];
             }
             counts[g * 21] = tot;

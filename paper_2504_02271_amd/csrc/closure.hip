@@ -100,76 +100,122 @@ __device__ __forceinline__ void flush_wave_counts(unsigned long long &wcnt, unsi
 
 constexpr int kUnroll = 4;   // partner-list entries per lane per step
 
-// Find the slot of key kk = (k << wbits) in the bucketed open-addressing
-// table (two (entry, position) slots per 16-byte bucket, buckets probed
-// linearly; a bucket's second slot fills after its first).  Returns whether
-// it is present; slot in out.
-__device__ __forceinline__ bool lookup(const uint2 *tab, uint32_t kk, uint32_t kmask, int wbits, int hbits,
-                                       uint2 &out) {
+// What a probe needs of the partner j: |e_j|, omega_rj, Omega_rj (mask
+// words over the owner's members), whether the common-vertex shortcut can
+// apply to j at all, and j's rank (for the member merge of owners without a
+// stored mask).
+struct JParams {
+    int sj, wij;
+    bool fast;
+    uint32_t m0, m1, m2, m3;
+    int32_t jr;
+};
+
+// kUnroll partner-list entries e[u] = (k, omega_jk) per lane against the
+// chunk of owner r staged in the bucketed open-addressing table (two
+// (entry, position) slots per 16-byte bucket, buckets probed linearly; a
+// bucket's second slot fills after its first).  The work goes in phases so
+// that each phase's LDS reads are in flight together: the first buckets;
+// slot selection; the rare continuation past a full bucket; size and mask
+// word of each k found; the common-vertex shortcut (all three omegas equal
+// omega_rj, Omega_rk = Omega_rj and every hyperedge larger than that: the
+// triple shares exactly those vertices); region classification for the
+// other hits.  hit[u]: entry u closes a hyper-triangle; mhit[u]: it counts
+// towards the per-hyperedge counts; po[u]: its pattern unless it is the
+// common-vertex one (counted in c9), else 0.
+template <bool PER_EDGE, typename JF>
+__device__ __forceinline__ void probe_tile(const uint2 *tab, int hbits, int wbits, uint32_t wmask,
+                                           const uint32_t (&e)[kUnroll], const bool (&val)[kUnroll],
+                                           const JF &jparams, const uint2 *ent_sm, const uint32_t *ent_mx,
+                                           uint32_t *ent_ck, const uint8_t *lut, int W, int si, const GraphDesc &G,
+                                           int32_t r, uint32_t emask, unsigned long long &c9,
+                                           bool (&hit)[kUnroll], bool (&mhit)[kUnroll], uint32_t (&po)[kUnroll]) {
     const uint4 *tq = reinterpret_cast<const uint4 *>(tab);
     const uint32_t nbm1 = (1u << (hbits - 1)) - 1;
-    uint32_t b = hslot(kk >> wbits, hbits - 1);
-    uint4 B = tq[b];
-    bool h0 = ((B.x & kmask) == kk) & (B.y != kEmptyPos);
-    bool h1 = ((B.z & kmask) == kk) & (B.w != kEmptyPos);
-    while (!(h0 | h1 | (B.w == kEmptyPos))) {      // full bucket without the key: next one
-        b = (b + 1) & nbm1;
-        B = tq[b];
-        h0 = ((B.x & kmask) == kk) & (B.y != kEmptyPos);
-        h1 = ((B.z & kmask) == kk) & (B.w != kEmptyPos);
+    const uint32_t kmask = ~wmask;
+    uint32_t b[kUnroll];
+    uint4 B[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; u++) b[u] = hslot(e[u] >> wbits, hbits - 1);
+#pragma unroll
+    for (int u = 0; u < kUnroll; u++) B[u] = tq[b[u]];
+    uint2 sl[kUnroll];
+    bool cont[kUnroll];
+    bool more = false;
+#pragma unroll
+    for (int u = 0; u < kUnroll; u++) {
+        const uint32_t kk = e[u] & kmask;
+        const bool h0 = ((B[u].x & kmask) == kk) & (B[u].y != kEmptyPos);
+        const bool h1 = ((B[u].z & kmask) == kk) & (B[u].w != kEmptyPos);
+        hit[u] = val[u] & (h0 | h1);
+        cont[u] = val[u] & !(h0 | h1) & (B[u].w != kEmptyPos);
+        more |= cont[u];
+        sl[u] = h0 ? make_uint2(B[u].x, B[u].y) : make_uint2(B[u].z, B[u].w);
     }
-    out = h0 ? make_uint2(B.x, B.y) : make_uint2(B.z, B.w);
-    return h0 | h1;
-}
-
-// One partner-list entry e = (k, omega_jk) of partner j against the staged
-// chunk of owner r.  hit: k lies in the chunk (a hyper-triangle r, j, k);
-// mhit: its pattern is counted into the per-hyperedge counts.  Returns the
-// pattern when it is not the common-vertex one (counted in c9), else 0.
-template <bool PER_EDGE>
-__device__ __forceinline__ uint32_t probe_entry(const uint2 *tab, int hbits, int wbits, uint32_t wmask, uint32_t e,
-                                                const uint2 *ent_sm, const uint32_t *ent_mx, uint32_t *ent_ck,
-                                                const uint8_t *lut, int W, int si, int sj, int wij, bool fast_j,
-                                                uint32_t m0, uint32_t m1, uint32_t m2, uint32_t m3,
-                                                const GraphDesc &G, int32_t r, int32_t jr, uint32_t emask,
-                                                unsigned long long &c9, bool &hit, bool &mhit) {
-    uint2 sl;
-    if (!lookup(tab, e & ~wmask, ~wmask, wbits, hbits, sl)) return 0u;
-    hit = true;
-    const uint32_t pos = sl.y;
-    const int wik = (int)(sl.x & wmask);
-    const int wjk = (int)(e & wmask);
-    const uint2 sm = ent_sm[pos];
-    // Omega_rk = Omega_rj and all three omegas equal: the triple shares
-    // exactly those vertices and nothing else
-    const bool fast = fast_j & (wik == wij) & (wjk == wij) & (sm.y == m0) & ((int)sm.x > wij);
-    uint32_t p = kPatternCommonVertex, other = 0u;
-    if (!fast) {
-        const uint32_t k = e >> wbits;
-        int g;
-        if (W > 0) {
-            g = __popc(m0 & sm.y);
-            if (W > 1) {
-                const uint32_t *mx = ent_mx + pos * (kMaskWordsMax - 1);
-                g += __popc(m1 & mx[0]);
-                if (W > 2) g += __popc(m2 & mx[1]);
-                if (W > 3) g += __popc(m3 & mx[2]);
+    if (more) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++) {
+            if (cont[u]) {
+                const uint32_t kk = e[u] & kmask;
+                uint32_t bb = b[u];
+                bool h0, h1;
+                uint4 Bx;
+                do {
+                    bb = (bb + 1) & nbm1;
+                    Bx = tq[bb];
+                    h0 = ((Bx.x & kmask) == kk) & (Bx.y != kEmptyPos);
+                    h1 = ((Bx.z & kmask) == kk) & (Bx.w != kEmptyPos);
+                } while (!(h0 | h1 | (Bx.w == kEmptyPos)));
+                hit[u] = h0 | h1;
+                sl[u] = h0 ? make_uint2(Bx.x, Bx.y) : make_uint2(Bx.z, Bx.w);
             }
-        } else {
-            g = triple_common(G.eptr, G.emem, r, jr, (int32_t)k);
-        }
-        const uint32_t m7 = region_mask(si, sj, (int)sm.x, wij, wik, wjk, g);
-        if (m7 != kMaskCommonVertex) {
-            p = lut[m7];
-            other = p;
         }
     }
-    c9 += (other == 0u);
-    if (PER_EDGE && ((emask >> p) & 1u)) {
-        mhit = true;
-        atomicAdd(&ent_ck[pos], 1u);
+    uint2 sm[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; u++) sm[u] = ent_sm[hit[u] ? sl[u].y : 0u];
+    bool fast[kUnroll];
+    bool slow = false;
+#pragma unroll
+    for (int u = 0; u < kUnroll; u++) {
+        const JParams J = jparams(u);
+        const int wik = (int)(sl[u].x & wmask), wjk = (int)(e[u] & wmask);
+        fast[u] = hit[u] & J.fast & (wik == J.wij) & (wjk == J.wij) & (sm[u].y == J.m0) & ((int)sm[u].x > J.wij);
+        c9 += fast[u];
+        po[u] = 0u;
+        slow |= hit[u] & !fast[u];
     }
-    return other;
+    if (slow) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++) {
+            if (hit[u] && !fast[u]) {
+                const JParams J = jparams(u);
+                const uint32_t pos = sl[u].y;
+                const int wik = (int)(sl[u].x & wmask), wjk = (int)(e[u] & wmask);
+                int g;
+                if (W > 0) {
+                    g = __popc(J.m0 & sm[u].y);
+                    if (W > 1) {
+                        const uint32_t *mx = ent_mx + pos * (kMaskWordsMax - 1);
+                        g += __popc(J.m1 & mx[0]);
+                        if (W > 2) g += __popc(J.m2 & mx[1]);
+                        if (W > 3) g += __popc(J.m3 & mx[2]);
+                    }
+                } else {
+                    g = triple_common(G.eptr, G.emem, r, J.jr, (int32_t)(e[u] >> wbits));
+                }
+                const uint32_t m7 = region_mask(si, J.sj, (int)sm[u].x, J.wij, wik, wjk, g);
+                if (m7 != kMaskCommonVertex) po[u] = lut[m7];
+                else c9++;
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; u++) {
+        const uint32_t p = po[u] ? po[u] : kPatternCommonVertex;
+        mhit[u] = PER_EDGE && hit[u] && ((emask >> p) & 1u);
+        if (PER_EDGE && mhit[u]) atomicAdd(&ent_ck[sl[u].y], 1u);
+    }
 }
 
 // Add the wave's other-pattern hits (po[u] != 0) into lane p's counter.
@@ -187,21 +233,66 @@ __device__ __forceinline__ void aggregate_other(const uint32_t *po, int lane, un
     }
 }
 
+// Shared memory of the closure kernel: the block layout (owner chunk and
+// partner segments of a block item) or, once the block items are drained,
+// one slice per wave for single-owner items.
+template <int CAP, int JP, bool PE, bool PW>
+struct CloseBlockLds {
+    uint2 tab[4 * CAP];                                // slots (entry, position); buckets of two
+    uint2 ent_sm[CAP];                                 // (|e_k|, Omega_rk word 0)
+    uint32_t ent_mx[CAP * (kMaskWordsMax - 1)];        // Omega_rk words 1..3
+    uint32_t ent_ck[PE ? CAP : 1];
+    int64_t seg_pre[kBlock + 1];
+    int64_t seg_src[JP];
+    uint32_t seg_size[JP];
+    uint32_t seg_om[JP];
+    uint32_t seg_mask[JP * kMaskWordsMax];
+    uint32_t seg_cj[PW ? JP : 1];
+    uint32_t seg_cjm[PE ? JP : 1];
+};
+struct CloseWaveLds {
+    uint2 tab[4 * kWaveOwnerMax];
+    uint2 ent_sm[kWaveOwnerMax];                       // (|e_k|, Omega_rk word 0); also the partner's data
+    uint32_t ent_mx[kWaveOwnerMax * (kMaskWordsMax - 1)];
+    uint32_t ent_ck[kWaveOwnerMax];
+    int64_t src[kWaveOwnerMax];                        // partner segment start minus its stream offset
+    uint32_t ent[kWaveOwnerMax];                       // packed entry (rank, omega) of N+(r)
+    int32_t incl[kWaveOwnerMax];                       // end of each partner segment in the stream
+    uint32_t cj[kWaveOwnerMax];
+    uint32_t cjm[kWaveOwnerMax];
+};
+template <int CAP, int JP, bool PE, bool PW>
+union CloseLds {
+    CloseBlockLds<CAP, JP, PE, PW> b;
+    CloseWaveLds w[kBlock / kWave];
+};
+
+// Order this wave's earlier LDS accesses before its later ones, across lanes
+// (LDS executes one wave's instructions in order once they are issued).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <int CAP, int JP, bool PER_EDGE, bool PER_WEDGE>
 __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
     static_assert(JP <= kBlock, "one thread per partner");
     constexpr int HMAX = 4 * CAP;
-    __shared__ __align__(16) uint2 tab[HMAX];        // slots (entry, position); buckets of two
-    __shared__ uint2 ent_sm[CAP];                         // (|e_k|, Omega_rk word 0)
-    __shared__ uint32_t ent_mx[CAP * (kMaskWordsMax - 1)];  // Omega_rk words 1..3
-    __shared__ uint32_t ent_ck[PER_EDGE ? CAP : 1];
-    __shared__ int64_t seg_pre[kBlock + 1];
-    __shared__ int64_t seg_src[JP];
-    __shared__ uint32_t seg_size[JP];
-    __shared__ uint32_t seg_om[JP];
-    __shared__ uint32_t seg_mask[JP * kMaskWordsMax];
-    __shared__ uint32_t seg_cj[PER_WEDGE ? JP : 1];
-    __shared__ uint32_t seg_cjm[PER_EDGE ? JP : 1];
+    static_assert(sizeof(CloseWaveLds) % 16 == 0, "wave slices keep the table 16-byte aligned");
+    __shared__ __align__(16) CloseLds<CAP, JP, PER_EDGE, PER_WEDGE> L;
+    uint2 *tab = L.b.tab;
+    uint2 *ent_sm = L.b.ent_sm;
+    uint32_t *ent_mx = L.b.ent_mx;
+    uint32_t *ent_ck = L.b.ent_ck;
+    int64_t *seg_pre = L.b.seg_pre;
+    int64_t *seg_src = L.b.seg_src;
+    uint32_t *seg_size = L.b.seg_size;
+    uint32_t *seg_om = L.b.seg_om;
+    uint32_t *seg_mask = L.b.seg_mask;
+    uint32_t *seg_cj = L.b.seg_cj;
+    uint32_t *seg_cjm = L.b.seg_cjm;
+    (void)HMAX;
     __shared__ uint8_t lut[128];
     __shared__ int64_t sh_item;
     __shared__ int64_t sh_scan[kBlock / kWave + 1];
@@ -308,7 +399,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
         const int64_t total = seg_pre[kBlock];
         all_probes += (unsigned long long)total;
 
-        // Partner-list entries go through probe_entry(); both loops below
+        // Partner-list entries go through probe_tile(); both loops below
         // keep the next tile's loads in flight while the current tile is
         // classified.
         if (total >= (int64_t)nseg * 64) {
@@ -368,18 +459,17 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                 const uint32_t m3 = W > 3 ? seg_mask[qd * kMaskWordsMax + 3] : 0u;
                 const bool fastd = (W == 1) && (si > wd) && (sjd > wd);
                 const int32_t jr = (W == 0) ? (int32_t)(gld(G.fadj + base + item.jb + qd) >> wbits) : 0;
+                const JParams Jd{sjd, wd, fastd, m0, m1, m2, m3, jr};
+                bool hit[kUnroll], mhit[kUnroll];
                 uint32_t po[kUnroll];
+                probe_tile<PER_EDGE>(tab, hbits, wbits, wmask, entA, valA, [&](int) { return Jd; }, ent_sm, ent_mx,
+                                     ent_ck, lut, W, si, G, r, A.emask, c9, hit, mhit, po);
                 bool other = false;
 #pragma unroll
                 for (int u = 0; u < kUnroll; u++) {
-                    bool hit = false, mhit = false;
-                    po[u] = valA[u] ? probe_entry<PER_EDGE>(tab, hbits, wbits, wmask, entA[u], ent_sm, ent_mx, ent_ck,
-                                                            lut, W, si, sjd, wd, fastd, m0, m1, m2, m3, G, r, jr,
-                                                            A.emask, c9, hit, mhit)
-                                    : 0u;
                     other |= po[u] != 0;
-                    if (PER_WEDGE) hits += (unsigned long long)__popcll(__ballot(hit));
-                    if (PER_EDGE) mhits += (unsigned long long)__popcll(__ballot(mhit));
+                    if (PER_WEDGE) hits += (unsigned long long)__popcll(__ballot(hit[u]));
+                    if (PER_EDGE) mhits += (unsigned long long)__popcll(__ballot(mhit[u]));
                 }
                 if (__ballot(other)) aggregate_other(po, lane, wcnt);
                 if (qn != qd) {
@@ -402,12 +492,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
             // a wave takes 64*kUnroll consecutive entries, kUnroll per lane.
             int qa = -1;                   // address cursor
             int64_t qa_end = 0, srca = 0;
-            int q = -1;                    // processing cursor
-            int sj = 0, wij = 0;
-            uint32_t mj0 = 0, mj1 = 0, mj2 = 0, mj3 = 0;
-            bool fast_j = false;
+            int q = -1;                    // segment whose counters this lane holds
             uint32_t cj = 0, cjm = 0;
-            int32_t jrank = 0;
             const int64_t stride = (int64_t)kBlock * kUnroll;
             auto fetch = [&](int64_t f0, uint32_t *ent, int *segu) {
 #pragma unroll
@@ -449,11 +535,29 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                         seguB[u] = -1;
                     }
                 }
+                bool valA[kUnroll], hit[kUnroll], mhit[kUnroll];
                 uint32_t po[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; u++) valA[u] = seguA[u] >= 0;
+                auto jf = [&](int u) {
+                    const int qq = seguA[u] < 0 ? 0 : seguA[u];
+                    JParams J;
+                    J.sj = (int)seg_size[qq];
+                    J.wij = (int)seg_om[qq];
+                    J.fast = (W == 1) && (si > J.wij) && (J.sj > J.wij);
+                    J.m0 = W > 0 ? seg_mask[qq * kMaskWordsMax + 0] : 0u;
+                    J.m1 = W > 1 ? seg_mask[qq * kMaskWordsMax + 1] : 0u;
+                    J.m2 = W > 2 ? seg_mask[qq * kMaskWordsMax + 2] : 0u;
+                    J.m3 = W > 3 ? seg_mask[qq * kMaskWordsMax + 3] : 0u;
+                    J.jr = (W == 0) ? (int32_t)(gld(G.fadj + base + item.jb + qq) >> wbits) : 0;
+                    return J;
+                };
+                probe_tile<PER_EDGE>(tab, hbits, wbits, wmask, entA, valA, jf, ent_sm, ent_mx, ent_ck, lut, W, si, G,
+                                     r, A.emask, c9, hit, mhit, po);
                 bool other = false;
 #pragma unroll
                 for (int u = 0; u < kUnroll; u++) {
-                    po[u] = 0;
+                    other |= po[u] != 0;
                     if (seguA[u] < 0) continue;
                     if (seguA[u] != q) {
                         if (q >= 0) {
@@ -462,22 +566,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                         }
                         cj = cjm = 0;
                         q = seguA[u];
-                        sj = (int)seg_size[q];
-                        wij = (int)seg_om[q];
-                        fast_j = (W == 1) && (si > wij) && (sj > wij);
-                        mj0 = W > 0 ? seg_mask[q * kMaskWordsMax + 0] : 0u;
-                        mj1 = W > 1 ? seg_mask[q * kMaskWordsMax + 1] : 0u;
-                        mj2 = W > 2 ? seg_mask[q * kMaskWordsMax + 2] : 0u;
-                        mj3 = W > 3 ? seg_mask[q * kMaskWordsMax + 3] : 0u;
-                        if (W == 0) jrank = (int32_t)(gld(G.fadj + base + item.jb + q) >> wbits);
                     }
-                    bool hit = false, mhit = false;
-                    po[u] = probe_entry<PER_EDGE>(tab, hbits, wbits, wmask, entA[u], ent_sm, ent_mx, ent_ck, lut, W,
-                                                  si, sj, wij, fast_j, mj0, mj1, mj2, mj3, G, r, jrank, A.emask, c9,
-                                                  hit, mhit);
-                    other |= po[u] != 0;
-                    cj += hit;
-                    cjm += mhit;
+                    cj += hit[u];
+                    cjm += mhit[u];
                 }
                 if (__ballot(other)) aggregate_other(po, lane, wcnt);
 #pragma unroll
@@ -513,32 +604,196 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
             }
         }
     }
-    if (cur_g >= 0) flush_wave_counts(wcnt, c9, A.counts, cur_g, lane);
     if (tid == 0 && all_probes) atomicAdd(A.probes, all_probes);
+
+    // Single-owner items, one wave each, in the wave's own LDS slice: the
+    // block items are drained and every wave of the block has passed the
+    // loop's last barrier, so the block layout is dead.  No block barrier
+    // from here on.
+    CloseWaveLds &Wl = L.w[wave];
+    unsigned long long wprobes = 0;
+    for (;;) {
+        unsigned int c = 0;
+        if (lane == 0) c = atomicAdd(A.wqueue, 1u);
+        c = (unsigned int)__builtin_amdgcn_readfirstlane((int)c);
+        if ((int64_t)c >= A.nwitems) break;
+        const Item item = A.witems[A.nwitems - 1 - (int64_t)c];
+        if (item.g != cur_g) {
+            if (cur_g >= 0) flush_wave_counts(wcnt, c9, A.counts, cur_g, lane);
+            cur_g = item.g;
+        }
+        const GraphDesc G = A.graphs[item.g];
+        const int wbits = G.wbits;
+        const uint32_t wmask = (1u << wbits) - 1;
+        const int32_t r = item.r;
+        const int64_t base = gld(G.fptr + r);
+        const int d = item.ce;                 // all of N+(r); partners are entries 0 .. d-2
+        const int si = gld(G.esize + r);
+        const int W = mask_words(si);
+        const int64_t mbase = gld(G.mptr + r);
+        int hbits = 6;
+        while ((1 << hbits) < 4 * d) hbits++;
+        const int H = 1 << hbits;              // <= 4 * kWaveOwnerMax
+        wave_lds_sync();                       // the previous owner's reads are done
+        for (int t = lane; t < H; t += kWave) Wl.tab[t] = make_uint2(0xFFFFFFFFu, kEmptyPos);
+        wave_lds_sync();
+        // lane q holds entry q of N+(r): the third hyperedge k = j_q of the
+        // chunk role and the partner j_q of the wedge (r, j_q)
+        int64_t len = 0, a = 0;
+        if (lane < d) {
+            const uint32_t ent = gld(G.fadj + base + lane);
+            const uint32_t k = ent >> wbits;
+            const int64_t mo = mbase + (int64_t)lane * W;
+            Wl.ent_sm[lane] = make_uint2((uint32_t)gld(G.esize + k), W > 0 ? gld(G.fmask + mo) : 0u);
+            for (int w = 1; w < W; w++) Wl.ent_mx[lane * (kMaskWordsMax - 1) + (w - 1)] = gld(G.fmask + mo + w);
+            Wl.ent[lane] = ent;
+            if (PER_EDGE) Wl.ent_ck[lane] = 0;
+            Wl.cj[lane] = 0;
+            Wl.cjm[lane] = 0;
+            uint32_t slot = hslot(k, hbits - 1) * 2;
+            while (atomicCAS(&Wl.tab[slot].y, kEmptyPos, (uint32_t)lane) != kEmptyPos) slot = (slot + 1) & (H - 1);
+            Wl.tab[slot].x = ent;
+            if (lane < d - 1) {
+                a = gld(G.fptr + k);
+                len = gld(G.fptr + k + 1) - a;
+            }
+        }
+        int64_t incl = len;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int64_t u = __shfl_up(incl, o, kWave);
+            if (lane >= o) incl += u;
+        }
+        const int64_t total = __shfl(incl, kWave - 1, kWave);   // lanes >= d-1 add nothing
+        if (lane < d - 1) {
+            Wl.incl[lane] = (int32_t)incl;
+            Wl.src[lane] = a - (incl - len);
+        }
+        wave_lds_sync();
+        wprobes += (unsigned long long)total;
+        // the partner lists end to end, kUnroll consecutive entries per lane
+        int qa = 0;                            // search cursor (monotone per lane)
+        int q = -1;                            // segment whose counters this lane holds
+        uint32_t cj = 0, cjm = 0;
+        for (int64_t fb = 0; fb < total; fb += (int64_t)kWave * kUnroll) {
+            uint32_t ent4[kUnroll];
+            int seg4[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; u++) {
+                const int64_t f = fb + (int64_t)lane * kUnroll + u;
+                seg4[u] = -1;
+                ent4[u] = 0u;
+                if (f < total) {
+                    while (Wl.incl[qa] <= f) qa++;     // ends at a segment <= d-2 since f < total
+                    seg4[u] = qa;
+                    ent4[u] = gld(G.fadj + Wl.src[qa] + f);
+                }
+            }
+            bool val4[kUnroll], hit[kUnroll], mhit[kUnroll];
+            uint32_t po[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; u++) val4[u] = seg4[u] >= 0;
+            auto jf = [&](int u) {
+                const int qq = seg4[u] < 0 ? 0 : seg4[u];
+                const uint2 jsm = Wl.ent_sm[qq];
+                const uint32_t jent = Wl.ent[qq];
+                JParams J;
+                J.sj = (int)jsm.x;
+                J.wij = (int)(jent & wmask);
+                J.fast = (W == 1) && (si > J.wij) && (J.sj > J.wij);
+                J.m0 = jsm.y;
+                J.m1 = W > 1 ? Wl.ent_mx[qq * (kMaskWordsMax - 1) + 0] : 0u;
+                J.m2 = W > 2 ? Wl.ent_mx[qq * (kMaskWordsMax - 1) + 1] : 0u;
+                J.m3 = W > 3 ? Wl.ent_mx[qq * (kMaskWordsMax - 1) + 2] : 0u;
+                J.jr = (int32_t)(jent >> wbits);
+                return J;
+            };
+            probe_tile<PER_EDGE>(Wl.tab, hbits, wbits, wmask, ent4, val4, jf, Wl.ent_sm, Wl.ent_mx, Wl.ent_ck, lut,
+                                 W, si, G, r, A.emask, c9, hit, mhit, po);
+            bool other = false;
+#pragma unroll
+            for (int u = 0; u < kUnroll; u++) {
+                other |= po[u] != 0;
+                if (seg4[u] < 0) continue;
+                if (seg4[u] != q) {
+                    if (q >= 0) {
+                        if (PER_WEDGE && cj) atomicAdd(&Wl.cj[q], cj);
+                        if (PER_EDGE && cjm) atomicAdd(&Wl.cjm[q], cjm);
+                    }
+                    cj = cjm = 0;
+                    q = seg4[u];
+                }
+                cj += hit[u];
+                cjm += mhit[u];
+            }
+            if (__ballot(other)) aggregate_other(po, lane, wcnt);
+        }
+        if (q >= 0) {
+            if (PER_WEDGE && cj) atomicAdd(&Wl.cj[q], cj);
+            if (PER_EDGE && cjm) atomicAdd(&Wl.cjm[q], cjm);
+        }
+        wave_lds_sync();
+        if (PER_WEDGE || PER_EDGE) {
+            if (lane < d - 1) {
+                if (PER_WEDGE) A.cwj[base + lane] = Wl.cj[lane];
+                if (PER_EDGE) A.cwjm[base + lane] = Wl.cjm[lane];
+            }
+            if (PER_EDGE && lane < d) A.cwkm[base + lane] = Wl.ent_ck[lane];
+        }
+    }
+    if (lane == 0 && wprobes) atomicAdd(A.probes, wprobes);
+    if (cur_g >= 0) flush_wave_counts(wcnt, c9, A.counts, cur_g, lane);
 }
 
-// number of items per owner
-__global__ void k_item_counts(const int64_t *fptr, int64_t m, int cap, int jp, int64_t *cnt) {
+// Work items per owner: block items in cnt, and wcnt = 1 for an owner closed
+// by one wave (at most kWaveOwnerMax forward entries and at most
+// kWaveStreamMax entries in its partners' lists; it then has no block item).
+__global__ void k_item_counts(const int64_t *fptr, const uint32_t *fadj, int wbits, int64_t m, int64_t owner_end,
+                              int cap, int jp, int64_t *cnt, int64_t *wcnt) {
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
          r += (int64_t)gridDim.x * blockDim.x) {
-        int64_t d = fptr[r + 1] - fptr[r];
+        const int64_t base = fptr[r];
+        const int64_t d = fptr[r + 1] - base;
         int64_t c = 0;
-        if (d >= 2) {
-            for (int64_t cb = 0; cb < d; cb += cap) {
-                int64_t ce = cb + cap < d ? cb + cap : d;
-                c += (ce - 1 + jp - 1) / jp;
+        bool wave = false;
+        if (d >= 2 && r < owner_end) {
+            if (d <= kWaveOwnerMax) {
+                int64_t sz = 0;
+                for (int64_t e = base; e < base + d - 1; e++) {
+                    const uint32_t j = fadj[e] >> wbits;
+                    sz += fptr[j + 1] - fptr[j];
+                }
+                wave = sz <= kWaveStreamMax;
+            }
+            if (!wave) {
+                for (int64_t cb = 0; cb < d; cb += cap) {
+                    int64_t ce = cb + cap < d ? cb + cap : d;
+                    c += (ce - 1 + jp - 1) / jp;
+                }
             }
         }
         cnt[r] = c;
+        wcnt[r] = wave ? 1 : 0;
     }
 }
 
-__global__ void k_item_fill(const int64_t *fptr, int64_t m, int cap, int jp, int32_t gid, const int64_t *ioff,
-                            Item *items) {
+__global__ void k_item_fill(const int64_t *fptr, int64_t m, int64_t owner_end, int cap, int jp, int32_t gid,
+                            const int64_t *ioff, const int64_t *woff, Item *items, Item *witems) {
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
          r += (int64_t)gridDim.x * blockDim.x) {
-        int64_t d = fptr[r + 1] - fptr[r];
-        if (d < 2) continue;
+        const int64_t d = fptr[r + 1] - fptr[r];
+        if (d < 2 || r >= owner_end) continue;
+        if (woff[r + 1] != woff[r]) {
+            Item it;
+            it.g = gid;
+            it.r = (int32_t)r;
+            it.cb = 0;
+            it.ce = (int32_t)d;
+            it.jb = 0;
+            it.je = (int32_t)(d - 1);
+            witems[woff[r]] = it;
+            continue;
+        }
         int64_t o = ioff[r];
         for (int64_t cb = 0; cb < d; cb += cap) {
             int64_t ce = cb + cap < d ? cb + cap : d;
@@ -557,38 +812,56 @@ __global__ void k_item_fill(const int64_t *fptr, int64_t m, int cap, int jp, int
     }
 }
 
-// S = sum over hyperwedges (r, j) of |N+(j)|
-__global__ void k_stream_size(const int64_t *fptr, const uint32_t *fadj, int64_t nw, int wbits,
+// S = sum over hyperwedges (r, j) of |N+(j)|; S[1] the same over the
+// hyperwedges at positions < e_split (the owners before the dense window)
+__global__ void k_stream_size(const int64_t *fptr, const uint32_t *fadj, int64_t nw, int64_t e_split, int wbits,
                               unsigned long long *S) {
-    __shared__ unsigned long long sh[256];
-    unsigned long long acc = 0;
+    __shared__ unsigned long long sh[256], sh2[256];
+    unsigned long long acc = 0, acc2 = 0;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nw;
          e += (int64_t)gridDim.x * blockDim.x) {
         uint32_t j = fadj[e] >> wbits;
-        acc += (unsigned long long)(fptr[j + 1] - fptr[j]);
+        const unsigned long long l = (unsigned long long)(fptr[j + 1] - fptr[j]);
+        acc += l;
+        if (e < e_split) acc2 += l;
     }
     sh[threadIdx.x] = acc;
+    sh2[threadIdx.x] = acc2;
     __syncthreads();
     for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        if ((int)threadIdx.x < o) {
+            sh[threadIdx.x] += sh[threadIdx.x + o];
+            sh2[threadIdx.x] += sh2[threadIdx.x + o];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicAdd(S, sh[0]);
+    if (threadIdx.x == 0) {
+        atomicAdd(S, sh[0]);
+        atomicAdd(S + 1, sh2[0]);
+    }
 }
 
-// per-hyperedge counts from the per-wedge role counters
-__global__ void k_edge_counts(const int64_t *fptr, const uint32_t *fadj, int64_t m, int wbits,
-                              const uint32_t *cwjm, const uint32_t *cwkm, unsigned long long *t) {
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m;
-         r += (int64_t)gridDim.x * blockDim.x) {
+// per-hyperedge counts from the per-wedge role counters: the j- and k-role
+// counts of hyperwedge (r, x) go to x (one thread per hyperwedge) ...
+__global__ void k_edge_counts_roles(const uint32_t *fadj, int64_t nw, int wbits, const uint32_t *cwjm,
+                                    const uint32_t *cwkm, unsigned long long *t) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nw; e += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t c = cwjm[e] + cwkm[e];
+        if (c) atomicAdd(&t[fadj[e] >> wbits], (unsigned long long)c);
+    }
+}
+
+// ... and the j-role counts of r's hyperwedges to r (one wave per owner)
+__global__ void k_edge_counts_owner(const int64_t *fptr, int64_t m, const uint32_t *cwjm, unsigned long long *t) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; r < m; r += nwaves) {
+        const int64_t b = fptr[r + 1];
         unsigned long long own = 0;
-        for (int64_t e = fptr[r]; e < fptr[r + 1]; e++) {
-            uint32_t x = fadj[e] >> wbits;
-            uint32_t c = cwjm[e] + cwkm[e];
-            if (c) atomicAdd(&t[x], (unsigned long long)c);
-            own += cwjm[e];
-        }
-        if (own) atomicAdd(&t[r], own);
+        for (int64_t e = fptr[r] + lane; e < b; e += kWave) own += cwjm[e];
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) own += __shfl_xor(own, o, kWave);
+        if (lane == 0 && own) atomicAdd(&t[r], own);
     }
 }
 
@@ -658,29 +931,404 @@ GraphDesc graph_desc(const Graph &g) {
     return d;
 }
 
-int64_t build_items(Graph &g, int32_t gid, const CloseConfig &cfg, DBuf<Item> &out) {
+void build_items(Graph &g, int32_t gid, const CloseConfig &cfg, ItemLists &out, int64_t owner_end) {
     hipStream_t s = g.stream;
     Allocator &A = g.al;
     const int64_t m = g.m;
-    DBuf<int64_t> icnt(A, m + 1);
+    DBuf<int64_t> icnt(A, m + 1), wcnt(A, m + 1);
     if (m > 0) {
-        hipLaunchKernelGGL(k_item_counts, dim3(grid_for(m, 256)), dim3(256), 0, s, g.fptr.p, m, cfg.cap, cfg.jp,
-                           icnt.p);
+        hipLaunchKernelGGL(k_item_counts, dim3(grid_for(m, 256)), dim3(256), 0, s, g.fptr.p, g.fadj.p, g.wbits, m,
+                           owner_end, cfg.cap, cfg.jp, icnt.p, wcnt.p);
         HTRI_LAUNCH_CHECK();
     }
     scan_exclusive_i64(A, icnt.p, icnt.p, m, icnt.p + m, s);
-    int64_t nitems = 0;
-    HTRI_HIP(hipMemcpyAsync(&nitems, icnt.p + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    scan_exclusive_i64(A, wcnt.p, wcnt.p, m, wcnt.p + m, s);
+    int64_t tot[2] = {0, 0};
+    HTRI_HIP(hipMemcpyAsync(&tot[0], icnt.p + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HTRI_HIP(hipMemcpyAsync(&tot[1], wcnt.p + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HTRI_HIP(hipStreamSynchronize(s));
-    if (nitems >= (int64_t)UINT32_MAX) fail(HTRI_E_UNSUPPORTED, "too many work items");
-    out.alloc(A, nitems);
-    if (m > 0 && nitems > 0) {
-        hipLaunchKernelGGL(k_item_fill, dim3(grid_for(m, 256)), dim3(256), 0, s, g.fptr.p, m, cfg.cap, cfg.jp, gid,
-                           icnt.p, out.p);
+    out.nblock = tot[0];
+    out.nwave = tot[1];
+    // the item counters are 32-bit and run past the end by one per block or wave
+    const int64_t limit = (int64_t)UINT32_MAX - ((int64_t)1 << 24);
+    if (out.nblock >= limit || out.nwave >= limit) fail(HTRI_E_UNSUPPORTED, "too many work items");
+    out.block.alloc(A, out.nblock);
+    out.wave.alloc(A, out.nwave);
+    if (m > 0 && out.nblock + out.nwave > 0) {
+        hipLaunchKernelGGL(k_item_fill, dim3(grid_for(m, 256)), dim3(256), 0, s, g.fptr.p, m, owner_end, cfg.cap,
+                           cfg.jp, gid, icnt.p, wcnt.p, out.block.p, out.wave.p);
         HTRI_LAUNCH_CHECK();
     }
     HTRI_HIP(hipStreamSynchronize(s));
-    return nitems;
+}
+
+// ---------------------------------------------------------------- dense window
+
+namespace {
+
+// The owners of the top ranks [w0, m) are closed by bitmap intersection.
+// Every forward neighbour of such an owner also lies in [w0, m), so each
+// hyperedge x of the window gets a row bitmap over the window: BF_x =
+// N+(x), BF1_x = its entries with omega = 1, and BI1_x = {j : x in N+(j),
+// omega_jx = 1} (the transpose of BF1), plus exclusive popcount prefixes of
+// BF_x per 32-bit word (position of an entry in N+(x)).  The closure of a
+// hyperwedge (r, j) is then |BF_r & BF_j|.  The common-vertex pattern is
+// counted in bulk: for a class K_v = {k in N+(r) : omega_rk = 1, Omega_rk =
+// {v}, |e_k| > 1} (v one vertex of e_r), a partner j in K_v closes a
+// common-vertex triangle with exactly the k in K_v with omega_jk = 1 (the
+// three pairwise intersections are then all {v} and every hyperedge has a
+// private vertex), i.e. |K_v & BF1_j|.  The owner's kWinClasses largest
+// classes are counted this way; the other hits are enumerated bit by bit and
+// classified by their regions like probed hits.
+constexpr int kWinRowsMax = 16384;
+constexpr int kWinWordsMax = kWinRowsMax / 32;
+constexpr int kWinClasses = 8;
+
+__global__ __launch_bounds__(256) void k_window_rows(const int64_t *fptr, const uint32_t *fadj, int wbits, int64_t w0,
+                                                     int nwords, uint32_t *bf, uint32_t *bf1, uint32_t *bi1,
+                                                     uint16_t *pf) {
+    __shared__ uint32_t rf[kWinWordsMax], r1[kWinWordsMax];
+    __shared__ uint32_t wsum[256 / kWave];
+    const int tid = threadIdx.x;
+    const int row = blockIdx.x;
+    const uint32_t wmask = (1u << wbits) - 1;
+    for (int w = tid; w < nwords; w += blockDim.x) rf[w] = r1[w] = 0u;
+    __syncthreads();
+    const int64_t b = fptr[w0 + row], e = fptr[w0 + row + 1];
+    for (int64_t i = b + tid; i < e; i += blockDim.x) {
+        const uint32_t ent = fadj[i];
+        const int kr = (int)((int64_t)(ent >> wbits) - w0);          // in (row, nrows)
+        atomicOr(&rf[kr >> 5], 1u << (kr & 31));
+        if ((ent & wmask) == 1u) {
+            atomicOr(&r1[kr >> 5], 1u << (kr & 31));
+            atomicOr(&bi1[(int64_t)kr * nwords + (row >> 5)], 1u << (row & 31));
+        }
+    }
+    __syncthreads();
+    // rows out; exclusive popcount prefix, two words per thread
+    const int w_a = 2 * tid, w_b = 2 * tid + 1;
+    const int ca = w_a < nwords ? __popc(rf[w_a]) : 0, cb = w_b < nwords ? __popc(rf[w_b]) : 0;
+    int incl = ca + cb;
+    const int lane = tid & (kWave - 1), wv = tid / kWave;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int u = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += u;
+    }
+    if (lane == kWave - 1) wsum[wv] = incl;
+    __syncthreads();
+    int before = 0;
+    for (int q = 0; q < wv; q++) before += wsum[q];
+    const int ex = before + incl - ca - cb;
+    const int64_t ro = (int64_t)row * nwords;
+    if (w_a < nwords) {
+        bf[ro + w_a] = rf[w_a];
+        bf1[ro + w_a] = r1[w_a];
+        pf[ro + w_a] = (uint16_t)ex;
+    }
+    if (w_b < nwords) {
+        bf[ro + w_b] = rf[w_b];
+        bf1[ro + w_b] = r1[w_b];
+        pf[ro + w_b] = (uint16_t)(ex + ca);
+    }
+}
+
+struct WinArgs {
+    GraphDesc G;
+    int64_t w0;
+    int nrows, nwords;
+    const uint32_t *bf, *bf1, *bi1;
+    const uint16_t *pf;
+    const uint8_t *lut;
+    uint32_t emask;
+    unsigned int *queue;
+    unsigned long long *counts;     // [21]
+    unsigned long long *stats;      // [0] bitmap words read, [1] hits enumerated
+    uint32_t *cwj, *cwjm, *cwkm;
+};
+
+template <bool PER_EDGE, bool PER_WEDGE>
+__global__ __launch_bounds__(kBlock) void k_close_window(WinArgs A) {
+    __shared__ uint32_t BR[kWinWordsMax], BK[kWinClasses][kWinWordsMax];
+    __shared__ int32_t PR[kWinWordsMax];
+    __shared__ uint32_t cls[32 * kMaskWordsMax];
+    __shared__ int32_t cslot[32 * kMaskWordsMax];  // class slot of member position v, or -1
+    __shared__ int32_t wsum[kBlock / kWave];
+    __shared__ unsigned long long cnt[21];
+    __shared__ int sh_row, sh_nc;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const GraphDesc &G = A.G;
+    const int wbits = G.wbits;
+    const uint32_t wmask = (1u << wbits) - 1;
+    const int nwords = A.nwords;
+    const bool count9 = (A.emask >> kPatternCommonVertex) & 1u;
+    if (tid < 21) cnt[tid] = 0ull;
+    unsigned long long words_read = 0, enumerated = 0;
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) {
+            const unsigned int c = atomicAdd(A.queue, 1u);
+            sh_row = (int64_t)c < A.nrows ? (int)c : -1;
+        }
+        __syncthreads();
+        const int row = sh_row;
+        if (row < 0) break;
+        const int32_t r = (int32_t)(A.w0 + row);
+        const int64_t base = gld(G.fptr + r);
+        const int d = (int)(gld(G.fptr + r + 1) - base);
+        if (d < 2) continue;
+        const int si = gld(G.esize + r);
+        const int W = mask_words(si);
+        const int64_t mbase = gld(G.mptr + r);
+        for (int w = tid; w < nwords; w += kBlock) BR[w] = 0u;
+        if (tid < 32 * kMaskWordsMax) cls[tid] = 0u;
+        __syncthreads();
+        const bool classes = (W >= 1) && (si >= 2);
+        // member position of the single shared vertex of an omega = 1 entry
+        auto single_pos = [&](int64_t q) -> int {
+            for (int w = 0; w < W; w++) {
+                const uint32_t x = gld(G.fmask + mbase + q * W + w);
+                if (x) return 32 * w + __ffs(x) - 1;
+            }
+            return -1;
+        };
+        for (int q = tid; q < d; q += kBlock) {
+            const uint32_t ent = gld(G.fadj + base + q);
+            const int kr = (int)((int64_t)(ent >> wbits) - A.w0);
+            atomicOr(&BR[kr >> 5], 1u << (kr & 31));
+            if (classes && (ent & wmask) == 1u && gld(G.esize + (ent >> wbits)) > 1) {
+                const int v = single_pos(q);
+                if (v >= 0) atomicAdd(&cls[v], 1u);
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            // the kWinClasses largest classes with at least two members
+            int nc = 0;
+            const int npos = 32 * W;
+            for (int v = 0; v < 32 * kMaskWordsMax; v++) cslot[v] = -1;
+            if (classes) {
+                for (; nc < kWinClasses; nc++) {
+                    int best = -1;
+                    uint32_t bc = 1;
+                    for (int v = 0; v < npos; v++)
+                        if (cslot[v] < 0 && cls[v] > bc) { bc = cls[v]; best = v; }
+                    if (best < 0) break;
+                    cslot[best] = nc;
+                }
+            }
+            sh_nc = nc;
+        }
+        // exclusive popcount prefix of BR (positions in N+(r)), two words per thread
+        {
+            const int w_a = 2 * tid, w_b = 2 * tid + 1;
+            const int ca = w_a < nwords ? __popc(BR[w_a]) : 0, cb = w_b < nwords ? __popc(BR[w_b]) : 0;
+            int incl = ca + cb;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int u = __shfl_up(incl, o, kWave);
+                if (lane >= o) incl += u;
+            }
+            if (lane == kWave - 1) wsum[wave] = incl;
+            __syncthreads();
+            int before = 0;
+            for (int q = 0; q < wave; q++) before += wsum[q];
+            const int ex = before + incl - ca - cb;
+            if (w_a < nwords) PR[w_a] = ex;
+            if (w_b < nwords) PR[w_b] = ex + ca;
+        }
+        const int nc = sh_nc;
+        for (int t = tid; t < nc * nwords; t += kBlock) BK[t / nwords][t % nwords] = 0u;
+        __syncthreads();
+        // class slot of an entry of N+(r), or -1
+        auto class_of = [&](uint32_t ent, int64_t q) -> int {
+            if (nc == 0 || (ent & wmask) != 1u || gld(G.esize + (ent >> wbits)) <= 1) return -1;
+            const int v = single_pos(q);
+            return v >= 0 ? cslot[v] : -1;
+        };
+        if (nc > 0) {
+            for (int q = tid; q < d; q += kBlock) {
+                const uint32_t ent = gld(G.fadj + base + q);
+                const int c = class_of(ent, q);
+                if (c >= 0) {
+                    const int kr = (int)((int64_t)(ent >> wbits) - A.w0);
+                    atomicOr(&BK[c][kr >> 5], 1u << (kr & 31));
+                }
+            }
+        }
+        __syncthreads();
+        // k-role of the common-vertex triangles: for k in class c, |K_c & BI1_k|
+        if (PER_EDGE) {
+            for (int q = wave; q < d; q += kBlock / kWave) {
+                const uint32_t ent = gld(G.fadj + base + q);
+                const int kr = (int)((int64_t)(ent >> wbits) - A.w0);
+                const int c = count9 ? class_of(ent, q) : -1;
+                uint32_t kf = 0;
+                if (c >= 0) {
+                    const uint32_t *bik = A.bi1 + (int64_t)kr * nwords;
+                    for (int w = (row >> 5) + lane; w <= (kr >> 5); w += kWave) kf += __popc(BK[c][w] & gld(bik + w));
+                    words_read += (unsigned long long)((kr >> 5) - (row >> 5) + 1);
+#pragma unroll
+                    for (int o = kWave / 2; o > 0; o >>= 1) kf += __shfl_xor(kf, o, kWave);
+                }
+                if (lane == 0) A.cwkm[base + q] = kf;
+            }
+            __threadfence();
+            __syncthreads();
+        }
+        // partners: entries 0 .. d-2, one wave each
+        for (int q = wave; q < d - 1; q += kBlock / kWave) {
+            const uint32_t jent = gld(G.fadj + base + q);
+            const int32_t j = (int32_t)(jent >> wbits);
+            const int jr = j - (int32_t)A.w0;
+            const int wij = (int)(jent & wmask);
+            const int sj = gld(G.esize + j);
+            uint32_t mj[kMaskWordsMax] = {0u, 0u, 0u, 0u};
+            for (int w = 0; w < W; w++) mj[w] = gld(G.fmask + mbase + (int64_t)q * W + w);
+            const int cj = class_of(jent, q);
+            const bool dom = cj >= 0;
+            const int64_t jbase = gld(G.fptr + j);
+            const uint32_t *bfj = A.bf + (int64_t)jr * nwords;
+            const uint32_t *bf1j = A.bf1 + (int64_t)jr * nwords;
+            const uint16_t *pfj = A.pf + (int64_t)jr * nwords;
+            uint32_t all = 0, fast = 0, menum = 0;
+            for (int w = (jr >> 5) + lane; w < nwords; w += kWave) {
+                const uint32_t bw = gld(bfj + w);
+                const uint32_t a = BR[w] & bw;
+                all += __popc(a);
+                const uint32_t fs = dom ? (BK[cj][w] & gld(bf1j + w)) : 0u;
+                fast += __popc(fs);
+                uint32_t non = a & ~fs;
+                while (non) {
+                    const int bpos = __ffs(non) - 1;
+                    non &= non - 1;
+                    const uint32_t below = (1u << bpos) - 1u;
+                    const int pr = PR[w] + __popc(BR[w] & below);          // position of k in N+(r)
+                    const int pj = (int)gld(pfj + w) + __popc(bw & below); // position of k in N+(j)
+                    const uint32_t kent = gld(G.fadj + base + pr);
+                    const int32_t k = (int32_t)(kent >> wbits);
+                    const int wik = (int)(kent & wmask);
+                    const int wjk = (int)(gld(G.fadj + jbase + pj) & wmask);
+                    const int sk = gld(G.esize + k);
+                    int g;
+                    if (W > 0) {
+                        g = 0;
+                        for (int x = 0; x < W; x++) g += __popc(mj[x] & gld(G.fmask + mbase + (int64_t)pr * W + x));
+                    } else {
+                        g = triple_common(G.eptr, G.emem, r, j, k);
+                    }
+                    const uint32_t p = A.lut[region_mask(si, sj, sk, wij, wik, wjk, g)];
+                    atomicAdd(&cnt[p], 1ull);
+                    enumerated++;
+                    if (PER_EDGE && ((A.emask >> p) & 1u)) {
+                        menum++;
+                        atomicAdd(&A.cwkm[base + pr], 1u);
+                    }
+                }
+            }
+            words_read += (unsigned long long)(nwords - (jr >> 5)) * (dom ? 2u : 1u);
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) {
+                all += __shfl_xor(all, o, kWave);
+                fast += __shfl_xor(fast, o, kWave);
+                menum += __shfl_xor(menum, o, kWave);
+            }
+            if (lane == 0) {
+                if (fast) atomicAdd(&cnt[kPatternCommonVertex], (unsigned long long)fast);
+                if (PER_WEDGE) A.cwj[base + q] = all;
+                if (PER_EDGE) A.cwjm[base + q] = (count9 ? fast : 0u) + menum;
+            }
+        }
+    }
+    __syncthreads();
+    if (tid >= 1 && tid < 21 && cnt[tid]) atomicAdd(&A.counts[tid], cnt[tid]);
+    // words_read is per wave (lane 0's copy counts); enumerated is per lane
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) enumerated += __shfl_xor(enumerated, o, kWave);
+    if (lane == 0) {
+        atomicAdd(&A.stats[0], words_read);
+        atomicAdd(&A.stats[1], enumerated);
+    }
+}
+
+}  // namespace
+
+WindowPlan choose_window(Graph &g, uint32_t flags) {
+    WindowPlan w;
+    w.w0 = g.m;
+    if ((flags & HTRI_COUNT_NO_WINDOW) || g.m < 3 || g.nw == 0) return w;
+    auto fptr_at = [&](int64_t i) {
+        int64_t v = 0;
+        HTRI_HIP(hipMemcpyAsync(&v, g.fptr.p + i, sizeof(int64_t), hipMemcpyDeviceToHost, g.stream));
+        HTRI_HIP(hipStreamSynchronize(g.stream));
+        return v;
+    };
+    const int64_t e_end = fptr_at(g.m);
+    for (int64_t cand = kWinRowsMax; cand >= 1024; cand /= 2) {
+        const int64_t n = std::min<int64_t>(g.m, cand);
+        const int64_t w0 = g.m - n;
+        const int64_t inside = e_end - fptr_at(w0);
+        if (inside == 0) continue;
+        const double density = (double)inside / (0.5 * (double)n * (double)n);
+        if ((flags & HTRI_COUNT_WINDOW_ALWAYS) || density >= 1.0 / 16.0) {
+            w.w0 = w0;
+            w.nrows = (int)n;
+            w.nwords = (int)((n + 31) / 32);
+            w.wedges = inside;
+            return w;
+        }
+        if (n < cand) break;      // the whole graph was the candidate
+    }
+    return w;
+}
+
+void close_window(Graph &g, const WindowPlan &w, uint32_t emask, const uint8_t *lut_dev, unsigned long long *counts,
+                  unsigned long long *stats, uint32_t *cwj, uint32_t *cwjm, uint32_t *cwkm) {
+    if (w.nrows == 0) return;
+    hipStream_t s = g.stream;
+    Allocator &A = g.al;
+    const int64_t cells = (int64_t)w.nrows * w.nwords;
+    DBuf<uint32_t> bf(A, cells), bf1(A, cells), bi1(A, cells);
+    DBuf<uint16_t> pf(A, cells);
+    DBuf<unsigned int> queue(A, 1);
+    fill_u32(bi1.p, cells, 0, s);
+    fill_u32(queue.p, 1, 0, s);
+    hipLaunchKernelGGL(k_window_rows, dim3(w.nrows), dim3(256), 0, s, g.fptr.p, g.fadj.p, g.wbits, w.w0, w.nwords,
+                       bf.p, bf1.p, bi1.p, pf.p);
+    HTRI_LAUNCH_CHECK();
+    WinArgs a;
+    a.G = graph_desc(g);
+    a.w0 = w.w0;
+    a.nrows = w.nrows;
+    a.nwords = w.nwords;
+    a.bf = bf.p;
+    a.bf1 = bf1.p;
+    a.bi1 = bi1.p;
+    a.pf = pf.p;
+    a.lut = lut_dev;
+    a.emask = emask;
+    a.queue = queue.p;
+    a.counts = counts;
+    a.stats = stats;
+    a.cwj = cwj;
+    a.cwjm = cwjm;
+    a.cwkm = cwkm;
+    const bool pe = cwjm != nullptr, pw = cwj != nullptr;
+    int nb = 0;
+    hipError_t oe;
+    if (pe && pw) oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_close_window<true, true>, kBlock, 0);
+    else if (pe) oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_close_window<true, false>, kBlock, 0);
+    else if (pw) oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_close_window<false, true>, kBlock, 0);
+    else oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_close_window<false, false>, kBlock, 0);
+    if (oe != hipSuccess || nb < 1) nb = 1;
+    const int grid = (int)std::min<int64_t>((int64_t)device_cu_count() * nb, w.nrows);
+    if (pe && pw) hipLaunchKernelGGL((k_close_window<true, true>), dim3(grid), dim3(kBlock), 0, s, a);
+    else if (pe) hipLaunchKernelGGL((k_close_window<true, false>), dim3(grid), dim3(kBlock), 0, s, a);
+    else if (pw) hipLaunchKernelGGL((k_close_window<false, true>), dim3(grid), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_close_window<false, false>), dim3(grid), dim3(kBlock), 0, s, a);
+    HTRI_LAUNCH_CHECK();
+    // the bitmaps are freed when this returns: wait for the kernels
+    HTRI_HIP(hipStreamSynchronize(s));
 }
 
 // ---------------------------------------------------------------- LUT
@@ -762,28 +1410,33 @@ const uint8_t *pattern_lut() {
 
 // ---------------------------------------------------------------- driver
 
-void count_patterns(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev, uint32_t *cw_dev) {
+void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21], uint64_t *t_dev, uint32_t *cw_dev) {
     hipStream_t s = g.stream;
     Allocator &A = g.al;
     const int64_t m = g.m;
     const CloseConfig cfg;  // 512-entry chunks, 256 partners per item
-    hipEvent_t e0, e1, e2, e3;
+    hipEvent_t e0, e1, e2, e3, ew;
     HTRI_HIP(hipEventCreate(&e0));
     HTRI_HIP(hipEventCreate(&e1));
     HTRI_HIP(hipEventCreate(&e2));
     HTRI_HIP(hipEventCreate(&e3));
+    HTRI_HIP(hipEventCreate(&ew));
     HTRI_HIP(hipEventRecord(e0, s));
 
-    DBuf<Item> items;
-    const int64_t nitems = build_items(g, 0, cfg, items);
+    const WindowPlan win = choose_window(g, flags);
+    const int64_t owner_end = win.nrows ? win.w0 : m;
+    ItemLists items;
+    build_items(g, 0, cfg, items, owner_end);
+    const int64_t nitems = items.nblock + items.nwave;
     DBuf<uint8_t> lut(A, 128);
     HTRI_HIP(hipMemcpyAsync(lut.p, pattern_lut(), 128, hipMemcpyHostToDevice, s));
     DBuf<GraphDesc> desc(A, 1);
     GraphDesc hd = graph_desc(g);
     HTRI_HIP(hipMemcpyAsync(desc.p, &hd, sizeof(GraphDesc), hipMemcpyHostToDevice, s));
-    // counters: queue (1), pattern counts (21), probes (1), S (1)
-    DBuf<unsigned long long> ctr(A, 24);
-    fill_u64((uint64_t *)ctr.p, 24, 0, s);
+    // counters: [0] block queue, [1..21] pattern counts, [22] probes,
+    // [23] wave queue, [24] S, [25] S before the window, [26..27] window stats
+    DBuf<unsigned long long> ctr(A, 28);
+    fill_u64((uint64_t *)ctr.p, 28, 0, s);
 
     const bool pe = t_dev != nullptr;
     const bool pw = cw_dev != nullptr;
@@ -802,9 +1455,12 @@ void count_patterns(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev
     HTRI_HIP(hipEventRecord(e1, s));
 
     CloseArgs a;
-    a.items = items.p;
-    a.nitems = nitems;
+    a.items = items.block.p;
+    a.nitems = items.nblock;
     a.queue = (unsigned int *)ctr.p;
+    a.witems = items.wave.p;
+    a.nwitems = items.nwave;
+    a.wqueue = (unsigned int *)(ctr.p + 23);
     a.graphs = desc.p;
     a.emask = mask;
     a.lut = lut.p;
@@ -813,20 +1469,32 @@ void count_patterns(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev
     a.cwkm = cwkm.p;
     a.counts = ctr.p + 1;
     a.probes = ctr.p + 22;
+    close_window(g, win, mask, lut.p, ctr.p + 1, ctr.p + 26, cw_dev, pe ? cwjm.p : nullptr, pe ? cwkm.p : nullptr);
+    HTRI_HIP(hipEventRecord(ew, s));
     launch_close_kernel(cfg, pe, pw, a, nblocks, s);
     HTRI_HIP(hipEventRecord(e2, s));
 
     if (g.nw > 0) {
+        int64_t e_split = g.nw;
+        if (win.nrows) {
+            HTRI_HIP(hipMemcpyAsync(&e_split, g.fptr.p + win.w0, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            HTRI_HIP(hipStreamSynchronize(s));
+        }
         hipLaunchKernelGGL(k_stream_size, dim3(grid_for(g.nw, 256, 2048)), dim3(256), 0, s, g.fptr.p, g.fadj.p, g.nw,
-                           g.wbits, ctr.p + 23);
+                           e_split, g.wbits, ctr.p + 24);
         HTRI_LAUNCH_CHECK();
     }
     if (pe) {
         DBuf<unsigned long long> t(A, m);
         fill_u64((uint64_t *)t.p, m, 0, s);
         if (m > 0) {
-            hipLaunchKernelGGL(k_edge_counts, dim3(grid_for(m, 256)), dim3(256), 0, s, g.fptr.p, g.fadj.p, m, g.wbits,
-                               cwjm.p, cwkm.p, t.p);
+            if (g.nw > 0) {
+                hipLaunchKernelGGL(k_edge_counts_roles, dim3(grid_for(g.nw, 256, 16384)), dim3(256), 0, s, g.fadj.p,
+                                   g.nw, g.wbits, cwjm.p, cwkm.p, t.p);
+                HTRI_LAUNCH_CHECK();
+            }
+            hipLaunchKernelGGL(k_edge_counts_owner, dim3(grid_for(m * kWave, 256, 8192)), dim3(256), 0, s, g.fptr.p, m,
+                               cwjm.p, t.p);
             HTRI_LAUNCH_CHECK();
             hipLaunchKernelGGL(k_rank_to_norm_u64, dim3(grid_for(m, 256)), dim3(256), 0, s, t.p, g.norm_of_rank.p, m,
                                (int64_t *)t_dev);
@@ -837,7 +1505,7 @@ void count_patterns(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev
     } else {
         HTRI_HIP(hipEventRecord(e3, s));
     }
-    unsigned long long hc[24];
+    unsigned long long hc[28];
     HTRI_HIP(hipMemcpyAsync(hc, ctr.p, sizeof(hc), hipMemcpyDeviceToHost, s));
     HTRI_HIP(hipStreamSynchronize(s));
     int64_t tot = 0;
@@ -847,20 +1515,36 @@ void count_patterns(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev
         tot += counts[p];
     }
     counts[0] = tot;
-    int64_t mask_words_total = 0;
-    HTRI_HIP(hipMemcpy(&mask_words_total, g.mptr.p + m, sizeof(int64_t), hipMemcpyDeviceToHost));
-    g.cstats[0] = (int64_t)hc[23];
+    int64_t mask_words_total = 0, mask_words_before = 0, wedges_before = g.nw;
+    HTRI_HIP(hipMemcpyAsync(&mask_words_total, g.mptr.p + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (win.nrows) {
+        HTRI_HIP(hipMemcpyAsync(&mask_words_before, g.mptr.p + win.w0, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HTRI_HIP(hipMemcpyAsync(&wedges_before, g.fptr.p + win.w0, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    }
+    HTRI_HIP(hipStreamSynchronize(s));
+    if (!win.nrows) mask_words_before = mask_words_total;
+    g.cstats[0] = (int64_t)hc[24];
     g.cstats[1] = (int64_t)hc[22];
     g.cstats[2] = nitems;
     g.cstats[3] = mask_words_total;
     g.cstats[4] = nblocks;
+    g.cstats[5] = win.nrows;
+    g.cstats[6] = win.wedges;
+    g.cstats[7] = (int64_t)hc[25];
+    g.cstats[8] = wedges_before;
+    g.cstats[9] = mask_words_before;
+    g.cstats[10] = (int64_t)hc[26];
+    g.cstats[11] = (int64_t)hc[27];
     HTRI_HIP(hipEventElapsedTime(&g.tm.schedule_ms, e0, e1));
     HTRI_HIP(hipEventElapsedTime(&g.tm.closure_ms, e1, e2));
+    HTRI_HIP(hipEventElapsedTime(&g.tm.window_ms, e1, ew));
+    HTRI_HIP(hipEventElapsedTime(&g.tm.probe_ms, ew, e2));
     HTRI_HIP(hipEventElapsedTime(&g.tm.reduce_ms, e2, e3));
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipEventDestroy(e2);
     (void)hipEventDestroy(e3);
+    (void)hipEventDestroy(ew);
 }
 
 }  // namespace htri

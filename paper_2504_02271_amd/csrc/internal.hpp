@@ -124,7 +124,7 @@ int device_cu_count();
 // ---------------------------------------------------------------- graph state
 
 struct Timings {
-    float wedges_ms = 0, schedule_ms = 0, closure_ms = 0, reduce_ms = 0;
+    float wedges_ms = 0, schedule_ms = 0, closure_ms = 0, reduce_ms = 0, window_ms = 0, probe_ms = 0;
 };
 
 struct Graph {
@@ -168,7 +168,7 @@ struct Graph {
     int64_t summary[6] = {0, 0, 0, 0, 0, 0};
 
     Timings tm;
-    int64_t cstats[5] = {0, 0, 0, 0, 0};
+    int64_t cstats[12] = {0};
 };
 
 // api.hip: message for htri_last_error(NULL)
@@ -203,9 +203,12 @@ struct CloseConfig {
     int jp = 256;
 };
 struct CloseArgs {
-    const Item *items;
+    const Item *items;              // block items (one block each)
     int64_t nitems;
-    unsigned int *queue;            // item counter, zero before the launch
+    unsigned int *queue;            // block-item counter, zero before the launch
+    const Item *witems;             // single-owner items (one wave each), taken after the block items
+    int64_t nwitems;
+    unsigned int *wqueue;           // single-owner item counter, zero before the launch
     const GraphDesc *graphs;
     uint32_t emask;                 // patterns counted into per-edge counts
     const uint8_t *lut;             // 128-entry region table
@@ -215,13 +218,31 @@ struct CloseArgs {
     unsigned long long *counts;     // [graphs][21]; [g][0] unused (total formed on the host)
     unsigned long long *probes;     // entries probed
 };
+// Owners with at most kWaveOwnerMax forward entries whose partner lists hold
+// at most kWaveStreamMax entries in total are closed by one wave each.
+constexpr int kWaveOwnerMax = 64;
+constexpr int64_t kWaveStreamMax = 1 << 16;
+struct ItemLists {
+    DBuf<Item> block, wave;
+    int64_t nblock = 0, nwave = 0;
+};
 GraphDesc graph_desc(const Graph &g);
-// items of one graph (graph index gid) for a configuration
-int64_t build_items(Graph &g, int32_t gid, const CloseConfig &cfg, DBuf<Item> &out);
+// work items of one graph (graph index gid) for a configuration; owners at
+// ranks >= owner_end get none (the dense window closes them)
+void build_items(Graph &g, int32_t gid, const CloseConfig &cfg, ItemLists &out, int64_t owner_end);
+// The dense window: owners [w0, m) closed by bitmap intersection.
+struct WindowPlan {
+    int64_t w0 = 0;
+    int nrows = 0, nwords = 0;
+    int64_t wedges = 0;
+};
+WindowPlan choose_window(Graph &g, uint32_t flags);
+void close_window(Graph &g, const WindowPlan &w, uint32_t emask, const uint8_t *lut_dev, unsigned long long *counts,
+                  unsigned long long *stats, uint32_t *cwj, uint32_t *cwjm, uint32_t *cwkm);
 int close_blocks_per_cu(const CloseConfig &cfg, bool pe, bool pw);
 void launch_close_kernel(const CloseConfig &cfg, bool pe, bool pw, const CloseArgs &a, int nblocks, hipStream_t s);
 bool valid_config(const CloseConfig &cfg);
-void count_patterns(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev /*m or null*/,
+void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21], uint64_t *t_dev /*m or null*/,
                     uint32_t *cw_dev /*nw or null*/);
 // sample.hip: closure of explicit wedges (per-sample counts) and weighted
 // sums over uniform (mode 1) or pool (mode 2) draws

@@ -20,6 +20,9 @@ HTRI_DEDUPE_EDGES = 1
 HTRI_INPUT_ON_DEVICE = 2
 HTRI_OUTPUT_ON_DEVICE = 4
 HTRI_ORDER_INPUT = 8
+HTRI_COUNT_NO_WINDOW = 16
+HTRI_COUNT_WINDOW_ALWAYS = 32
+_WINDOW_FLAGS = {"auto": 0, "off": HTRI_COUNT_NO_WINDOW, "always": HTRI_COUNT_WINDOW_ALWAYS}
 HTRI_MODEL_NUM_PARAMS = 5313
 ALL_PATTERNS = 0x1FFFFE
 
@@ -239,15 +242,16 @@ class Graph:
         return src, dst, om
 
     def count_patterns(self, mask: int = 0, per_edge: bool = False, per_wedge: bool = False,
-                       device_out: bool = False):
+                       device_out: bool = False, window: str = "auto"):
         """Returns (counts int64[21], per_edge or None, per_wedge or None).
-        With device_out the per-edge/per-wedge results are torch tensors on the GPU."""
+        With device_out the per-edge/per-wedge results are torch tensors on the GPU.
+        window: "auto" (dense top-rank window when it pays), "off", "always"."""
         counts = np.zeros(21, np.int64)
         pe = pw = None
-        flags = 0
+        flags = _WINDOW_FLAGS[window]
         if device_out:
             import torch
-            flags = HTRI_OUTPUT_ON_DEVICE
+            flags |= HTRI_OUTPUT_ON_DEVICE
             if per_edge:
                 pe = torch.empty(self.num_edges, dtype=torch.int64, device="cuda")
             if per_wedge:
@@ -270,8 +274,10 @@ class Graph:
         self.summary = None
 
     def closure_stats(self) -> np.ndarray:
-        """[S, probed entries, work items, Omega mask words, closure blocks]"""
-        out = np.zeros(5, np.int64)
+        """[S, probed entries, work items, Omega mask words, closure blocks,
+        window rows, window wedges, S outside the window, wedges outside,
+        mask words outside, window bitmap words read, window hits enumerated]"""
+        out = np.zeros(12, np.int64)
         _check(self._lib.htri_closure_stats(self._h, _ptr(out)), "htri_closure_stats", self._h)
         return out
 
@@ -305,7 +311,8 @@ class Graph:
         return x[: self.num_wedges]
 
     def last_timings(self) -> np.ndarray:
-        ms = np.zeros(4, np.float64)
+        """ms: [wedges, schedule, closure, reduce, window part, probing part]"""
+        ms = np.zeros(6, np.float64)
         _check(self._lib.htri_last_timings(self._h, _ptr(ms)), "htri_last_timings", self._h)
         return ms
 

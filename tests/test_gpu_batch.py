@@ -73,3 +73,24 @@ def test_batch_load_errors(htri):
     with pytest.raises(htri.HtriError) as e:
         htri.Batch([synth.from_lists([[0, 1], [1, 2]], 3), bad], flags=0)
     assert e.value.code == -4 and "graph 1" in str(e.value)
+
+
+def test_full_batch_of_512_graphs(htri):
+    """The 512-graph batch at full size: the batched replay equals the
+    per-graph launches on every graph, and the oracle on a sample of graphs
+    (the largest ones and a random draw)."""
+    specs = synth.batch_specs()
+    graphs = [synth.generate(s) for s in specs]
+    print(f"\n[batch512] {len(graphs)} graphs, {sum(g.num_edges for g in graphs)} hyperedges", flush=True)
+    B = htri.Batch(graphs)
+    sched, _ = B.autotune(repeats=1)
+    got, _ = B.count_patterns(sched, use_graph=True)
+    per, _ = B.count_per_graph((512, 256, 0))
+    assert np.array_equal(got, per)
+    sizes = np.array([g.num_edges for g in graphs])
+    rng = np.random.default_rng(3)
+    pick = np.unique(np.concatenate([np.argsort(sizes)[-3:], rng.choice(len(graphs), size=13, replace=False)]))
+    for q in pick:
+        g = graphs[q]
+        want = core.OracleGraph(g.offsets, g.members, g.num_vertices).count(per_edge=False).H
+        assert np.array_equal(got[q], want), q

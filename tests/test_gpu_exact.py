@@ -27,8 +27,9 @@ def _orient(rank, a, b):
     return lo, hi
 
 
-def check_exact(htri, g, flags=None, wedge_sample=None, nthreads=0, seed=0):
-    """Full parity on one hypergraph; returns (GPU graph, oracle graph, counts)."""
+def check_exact(htri, g, flags=None, wedge_sample=None, nthreads=0, seed=0, windows=("off", "always", "auto")):
+    """Full parity on one hypergraph, with the dense window forced off, forced
+    on and chosen automatically; returns (GPU graph, oracle graph, counts)."""
     if flags is None:
         flags = htri.HTRI_DEDUPE_EDGES
     print(f"\n[check_exact] {g.name} m={g.num_edges} nnz={g.nnz} flags={flags}", flush=True)
@@ -49,11 +50,7 @@ def check_exact(htri, g, flags=None, wedge_sample=None, nthreads=0, seed=0):
     got = np.lexsort((hi, lo))
     assert np.array_equal(lo[got], wi) and np.array_equal(hi[got], wj) and np.array_equal(om[got], wo)
     # a2 + a3: per-pattern and per-hyperedge counts, per-wedge closure
-    counts, pe, pw = G.count_patterns(per_edge=True, per_wedge=True)
     r = o.count(nthreads=nthreads)
-    assert np.array_equal(counts, r.H), (counts, r.H)
-    assert np.array_equal(pe, r.t)
-    assert int(pw.astype(np.int64).sum()) == int(counts[0])
     if flags & htri.HTRI_ORDER_INPUT:
         rank = np.arange(o.m, dtype=np.int64)
     else:
@@ -64,7 +61,18 @@ def check_exact(htri, g, flags=None, wedge_sample=None, nthreads=0, seed=0):
         rng = np.random.default_rng(seed)
         idx = np.sort(rng.choice(idx.shape[0], size=wedge_sample, replace=False))
     want = o.wedge_closure_ranked(rank, src[idx], dst[idx])[:, 0]
-    assert np.array_equal(pw[idx].astype(np.int64), want)
+    for win in windows:
+        counts, pe, pw = G.count_patterns(per_edge=True, per_wedge=True, window=win)
+        st = G.closure_stats()
+        print(f"[check_exact]   window={win}: rows {st[5]}, wedges inside {st[6]}, enumerated {st[11]}", flush=True)
+        if win == "always" and G.num_wedges > 0 and 3 <= G.num_edges <= 16384:
+            assert st[5] == G.num_edges
+        if win == "off":
+            assert st[5] == 0
+        assert np.array_equal(counts, r.H), (win, counts, r.H)
+        assert np.array_equal(pe, r.t), win
+        assert int(pw.astype(np.int64).sum()) == int(counts[0])
+        assert np.array_equal(pw[idx].astype(np.int64), want), win
     return G, o, counts
 
 
@@ -183,10 +191,11 @@ def test_pattern_mask_for_per_edge_counts(htri):
     G.build_wedges()
     o = core.OracleGraph(g.offsets, g.members, g.num_vertices)
     for mask in ((1 << 9), (1 << 1) | (1 << 5) | (1 << 17), 0x1FFFFE & ~(1 << 9)):
-        counts, pe, _ = G.count_patterns(mask=mask, per_edge=True)
         r = o.count(edge_mask=mask)
-        assert np.array_equal(counts, r.H)
-        assert np.array_equal(pe, r.t)
+        for win in ("off", "always"):
+            counts, pe, _ = G.count_patterns(mask=mask, per_edge=True, window=win)
+            assert np.array_equal(counts, r.H), (mask, win)
+            assert np.array_equal(pe, r.t), (mask, win)
 
 
 def test_device_input_and_output(htri):

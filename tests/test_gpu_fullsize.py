@@ -21,14 +21,28 @@ def full():
     G = htri.graph_load(g.offsets, g.members, g.num_vertices)
     s = G.build_wedges()
     counts, pe, pw = G.count_patterns(per_edge=True, per_wedge=True)
-    print(f"[fullsize] wedges {int(s[0])} triangles {int(counts[0])} stages ms {G.last_timings().tolist()}",
-          flush=True)
+    st = G.closure_stats()
+    print(f"[fullsize] wedges {int(s[0])} triangles {int(counts[0])} stages ms {G.last_timings().tolist()} "
+          f"window rows {st[5]} wedges inside {st[6]}", flush=True)
     src, dst, om = G.get_wedges()
     o = core.OracleGraph(g.offsets, g.members, g.num_vertices)
     off, mem, orig = o.csr()
     rank = core.prec_rank(off, mem, g.num_vertices)
     return dict(g=g, G=G, s=s, counts=counts, pe=pe, pw=pw, src=src, dst=dst, om=om, o=o, off=off, mem=mem,
                 rank=rank)
+
+
+def test_window_and_probing_agree(full):
+    """The dense window (on by default at this size) and the probing path
+    alone give the same counts, per-hyperedge counts and per-wedge closures."""
+    G = full["G"]
+    st = G.closure_stats()
+    c1, pe1, pw1 = G.count_patterns(per_edge=True, per_wedge=True, window="off")
+    assert G.closure_stats()[5] == 0
+    assert np.array_equal(c1, full["counts"])
+    assert np.array_equal(pe1, full["pe"])
+    assert np.array_equal(pw1, full["pw"])
+    print(f"\n[fullsize] window rows {st[5]}: probing alone agrees", flush=True)
 
 
 def test_invariants(full):
