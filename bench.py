@@ -40,15 +40,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def closure_bytes(summary, cstats):
-    """Algorithmic bytes of one closure launch: the probe stream (4 B packed
-    entry per partner-list entry, S of them), the owner lists staged once
-    (4 B entry + 4 B size of the third hyperedge per hyperwedge, plus the
-    Omega mask words), and the two 4 B per-wedge role counters written."""
-    nw = int(summary[0])
-    S = int(cstats[0])
-    mask_words = int(cstats[3])
-    return 4 * S + 8 * nw + 4 * mask_words + 8 * nw
+def closure_bytes(cstats):
+    """Algorithmic bytes of one launch of the probing closure kernel (the
+    owners outside the dense window): the probe stream (4 B packed entry per
+    partner-list entry, S of them), the owner lists staged once (4 B entry +
+    4 B size of the third hyperedge per hyperwedge, plus the Omega mask
+    words), and the two 4 B per-wedge role counters written."""
+    S_probe = int(cstats[7])
+    nw_probe = int(cstats[8])
+    mask_words = int(cstats[9])
+    return 4 * S_probe + 8 * nw_probe + 4 * mask_words + 8 * nw_probe
+
+
+def window_bytes(cstats):
+    """Algorithmic bytes of the dense-window closure: the bitmap words it
+    reads (4 B each)."""
+    return 4 * int(cstats[10])
 
 
 def closure_source_sha() -> str:
@@ -265,11 +272,14 @@ def main() -> int:
     stage_ms = np.array(stage_ms)
     cstats = G.closure_stats()
     close_ms = float(stage_ms[:, 2].mean())
-    B = closure_bytes(s, cstats)
-    achieved = B / (close_ms / 1e3) / 1e9
+    probe_ms = float(stage_ms[:, 5].mean())
+    win_ms = float(stage_ms[:, 4].mean())
+    B = closure_bytes(cstats)
+    achieved = B / (probe_ms / 1e3) / 1e9
+    BW = window_bytes(cstats)
     log(f"[bench] {args.steps} steps: {ms_per_step:.2f} ms/step; stages (wedges, schedule, closure, "
-        f"reduce) ms {np.round(stage_ms.mean(axis=0), 2).tolist()}; S={int(cstats[0])} "
-        f"probed={int(cstats[1])} items={int(cstats[2])}")
+        f"reduce, window part, probing part) ms {np.round(stage_ms.mean(axis=0), 2).tolist()}; "
+        f"closure stats {cstats.tolist()}")
 
     cpu = None
     if not args.no_cpu:
@@ -309,20 +319,31 @@ def main() -> int:
             "connected_triples_W": int(s[3]),
             "load_normalise_ms_incl_h2d": round(load_ms, 2),
             "stage_ms": {"wedges": float(stage_ms[:, 0].mean()), "schedule": float(stage_ms[:, 1].mean()),
-                         "closure": close_ms, "reduce": float(stage_ms[:, 3].mean())},
+                         "closure": close_ms, "closure_window": win_ms, "closure_probing": probe_ms,
+                         "reduce": float(stage_ms[:, 3].mean())},
             "triangles_per_s": int(counts[0]) / (ms_per_step / 1e3),
+            "closure_stream_S": int(cstats[0]),
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_close (closure + classify + per-block reduce)",
+            "kernel": "k_close (probing closure + classify + per-block reduce, owners outside the dense window)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "algorithmic_bytes": B,
-            "closure_stream_S": int(cstats[0]),
+            "probe_stream_S": int(cstats[7]),
             "entries_probed": int(cstats[1]),
+        },
+        "window": {
+            "kernels": "k_window_rows + k_close_window (owners of the top ranks, bitmap intersection)",
+            "rows": int(cstats[5]),
+            "hyperwedges_inside": int(cstats[6]),
+            "bitmap_bytes_read": BW,
+            "ms": win_ms,
+            "achieved_GBps": BW / (win_ms / 1e3) / 1e9 if win_ms > 0 else None,
+            "hits_enumerated": int(cstats[11]),
         },
         "cpu_baseline": cpu,
         "estimator": study,

@@ -111,7 +111,8 @@ struct JParams {
     int32_t jr;
 };
 
-// kUnroll partner-list entries e[u] = (k, omega_jk) per lane against the
+// kUnroll partner-list entries e[u] = (k, omega_jk) per lane (partner data
+// for the shortcut test in fwij / fm0 / ffast, the rest from jparams) against the
 // chunk of owner r staged in the bucketed open-addressing table (two
 // (entry, position) slots per 16-byte bucket, buckets probed linearly; a
 // bucket's second slot fills after its first).  The work goes in phases so
@@ -126,6 +127,8 @@ struct JParams {
 template <bool PER_EDGE, typename JF>
 __device__ __forceinline__ void probe_tile(const uint2 *tab, int hbits, int wbits, uint32_t wmask,
                                            const uint32_t (&e)[kUnroll], const bool (&val)[kUnroll],
+                                           const int (&fwij)[kUnroll], const uint32_t (&fm0)[kUnroll],
+                                           const bool (&ffast)[kUnroll],
                                            const JF &jparams, const uint2 *ent_sm, const uint32_t *ent_mx,
                                            uint32_t *ent_ck, const uint8_t *lut, int W, int si, const GraphDesc &G,
                                            int32_t r, uint32_t emask, unsigned long long &c9,
@@ -178,9 +181,9 @@ __device__ __forceinline__ void probe_tile(const uint2 *tab, int hbits, int wbit
     bool slow = false;
 #pragma unroll
     for (int u = 0; u < kUnroll; u++) {
-        const JParams J = jparams(u);
         const int wik = (int)(sl[u].x & wmask), wjk = (int)(e[u] & wmask);
-        fast[u] = hit[u] & J.fast & (wik == J.wij) & (wjk == J.wij) & (sm[u].y == J.m0) & ((int)sm[u].x > J.wij);
+        fast[u] = hit[u] & ffast[u] & (wik == fwij[u]) & (wjk == fwij[u]) & (sm[u].y == fm0[u]) &
+                  ((int)sm[u].x > fwij[u]);
         c9 += fast[u];
         po[u] = 0u;
         slow |= hit[u] & !fast[u];
@@ -367,7 +370,12 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
             len = b - a;
             seg_src[tid] = a;
             seg_size[tid] = (uint32_t)gld(G.esize + j);
-            seg_om[tid] = jent & wmask;
+            {
+                const uint32_t om = jent & wmask;
+                const uint32_t sz = (uint32_t)gld(G.esize + j);
+                const bool fj = (W == 1) && ((uint32_t)si > om) && (sz > om);
+                seg_om[tid] = om | (fj ? 0x80000000u : 0u);   // bit 31: the shortcut can apply to j
+            }
             for (int w = 0; w < W; w++) seg_mask[tid * kMaskWordsMax + w] = gld(G.fmask + mbase + (int64_t)pj * W + w);
             if (PER_WEDGE) seg_cj[tid] = 0;
             if (PER_EDGE) seg_cjm[tid] = 0;
@@ -402,7 +410,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
         // Partner-list entries go through probe_tile(); both loops below
         // keep the next tile's loads in flight while the current tile is
         // classified.
-        if (total >= (int64_t)nseg * 64) {
+        if (total >= (int64_t)nseg * 256) {
             // Dense items (long partner segments): one wave per partner, the
             // partner's data wave-uniform, lanes striding over its segment.
             constexpr int TILE = kWave * kUnroll;
@@ -452,7 +460,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                 }
                 // this tile
                 const int sjd = __builtin_amdgcn_readfirstlane((int)seg_size[qd]);
-                const int wd = __builtin_amdgcn_readfirstlane((int)seg_om[qd]);
+                const int wd = __builtin_amdgcn_readfirstlane((int)(seg_om[qd] & 0x7FFFFFFFu));
                 const uint32_t m0 = W > 0 ? (uint32_t)__builtin_amdgcn_readfirstlane((int)seg_mask[qd * kMaskWordsMax]) : 0u;
                 const uint32_t m1 = W > 1 ? seg_mask[qd * kMaskWordsMax + 1] : 0u;
                 const uint32_t m2 = W > 2 ? seg_mask[qd * kMaskWordsMax + 2] : 0u;
@@ -462,8 +470,17 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                 const JParams Jd{sjd, wd, fastd, m0, m1, m2, m3, jr};
                 bool hit[kUnroll], mhit[kUnroll];
                 uint32_t po[kUnroll];
-                probe_tile<PER_EDGE>(tab, hbits, wbits, wmask, entA, valA, [&](int) { return Jd; }, ent_sm, ent_mx,
-                                     ent_ck, lut, W, si, G, r, A.emask, c9, hit, mhit, po);
+                int fwij[kUnroll];
+                uint32_t fm0[kUnroll];
+                bool ffast[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; u++) {
+                    fwij[u] = wd;
+                    fm0[u] = m0;
+                    ffast[u] = fastd;
+                }
+                probe_tile<PER_EDGE>(tab, hbits, wbits, wmask, entA, valA, fwij, fm0, ffast, [&](int) { return Jd; },
+                                     ent_sm, ent_mx, ent_ck, lut, W, si, G, r, A.emask, c9, hit, mhit, po);
                 bool other = false;
 #pragma unroll
                 for (int u = 0; u < kUnroll; u++) {
@@ -539,11 +556,34 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                 uint32_t po[kUnroll];
 #pragma unroll
                 for (int u = 0; u < kUnroll; u++) valA[u] = seguA[u] >= 0;
+                // shortcut data per entry, reloaded only where the segment changes
+                int fwij[kUnroll];
+                uint32_t fm0[kUnroll];
+                bool ffast[kUnroll];
+                {
+                    int qc = -1, cw = 0;
+                    uint32_t cm = 0u;
+                    bool cf = false;
+#pragma unroll
+                    for (int u = 0; u < kUnroll; u++) {
+                        const int qq = seguA[u] < 0 ? 0 : seguA[u];
+                        if (qq != qc) {
+                            qc = qq;
+                            const uint32_t om = seg_om[qq];
+                            cw = (int)(om & 0x7FFFFFFFu);
+                            cf = (om >> 31) != 0u;
+                            cm = W > 0 ? seg_mask[qq * kMaskWordsMax + 0] : 0u;
+                        }
+                        fwij[u] = cw;
+                        fm0[u] = cm;
+                        ffast[u] = cf;
+                    }
+                }
                 auto jf = [&](int u) {
                     const int qq = seguA[u] < 0 ? 0 : seguA[u];
                     JParams J;
                     J.sj = (int)seg_size[qq];
-                    J.wij = (int)seg_om[qq];
+                    J.wij = (int)(seg_om[qq] & 0x7FFFFFFFu);
                     J.fast = (W == 1) && (si > J.wij) && (J.sj > J.wij);
                     J.m0 = W > 0 ? seg_mask[qq * kMaskWordsMax + 0] : 0u;
                     J.m1 = W > 1 ? seg_mask[qq * kMaskWordsMax + 1] : 0u;
@@ -552,8 +592,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                     J.jr = (W == 0) ? (int32_t)(gld(G.fadj + base + item.jb + qq) >> wbits) : 0;
                     return J;
                 };
-                probe_tile<PER_EDGE>(tab, hbits, wbits, wmask, entA, valA, jf, ent_sm, ent_mx, ent_ck, lut, W, si, G,
-                                     r, A.emask, c9, hit, mhit, po);
+                probe_tile<PER_EDGE>(tab, hbits, wbits, wmask, entA, valA, fwij, fm0, ffast, jf, ent_sm, ent_mx, ent_ck,
+                                     lut, W, si, G, r, A.emask, c9, hit, mhit, po);
                 bool other = false;
 #pragma unroll
                 for (int u = 0; u < kUnroll; u++) {
@@ -693,6 +733,28 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
             uint32_t po[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; u++) val4[u] = seg4[u] >= 0;
+            int fwij[kUnroll];
+            uint32_t fm0[kUnroll];
+            bool ffast[kUnroll];
+            {
+                int qc = -1, cw = 0;
+                uint32_t cm = 0u;
+                bool cf = false;
+#pragma unroll
+                for (int u = 0; u < kUnroll; u++) {
+                    const int qq = seg4[u] < 0 ? 0 : seg4[u];
+                    if (qq != qc) {
+                        qc = qq;
+                        const uint2 jsm = Wl.ent_sm[qq];
+                        cw = (int)(Wl.ent[qq] & wmask);
+                        cm = jsm.y;
+                        cf = (W == 1) && (si > cw) && ((int)jsm.x > cw);
+                    }
+                    fwij[u] = cw;
+                    fm0[u] = cm;
+                    ffast[u] = cf;
+                }
+            }
             auto jf = [&](int u) {
                 const int qq = seg4[u] < 0 ? 0 : seg4[u];
                 const uint2 jsm = Wl.ent_sm[qq];
@@ -708,8 +770,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                 J.jr = (int32_t)(jent >> wbits);
                 return J;
             };
-            probe_tile<PER_EDGE>(Wl.tab, hbits, wbits, wmask, ent4, val4, jf, Wl.ent_sm, Wl.ent_mx, Wl.ent_ck, lut,
-                                 W, si, G, r, A.emask, c9, hit, mhit, po);
+            probe_tile<PER_EDGE>(Wl.tab, hbits, wbits, wmask, ent4, val4, fwij, fm0, ffast, jf, Wl.ent_sm, Wl.ent_mx,
+                                 Wl.ent_ck, lut, W, si, G, r, A.emask, c9, hit, mhit, po);
             bool other = false;
 #pragma unroll
             for (int u = 0; u < kUnroll; u++) {
