@@ -221,3 +221,15 @@ def test_coauthorship_workload(htri):
     c2, pe2, pw2 = G.count_patterns(per_edge=True, per_wedge=True)
     c3, pe3, pw3 = G.count_patterns(per_edge=True, per_wedge=True)
     assert np.array_equal(c2, c3) and np.array_equal(pe2, pe3) and np.array_equal(pw2, pw3)
+
+
+def test_owner_with_many_incidences(htri):
+    """An owner meeting more incidences than an LDS tile holds goes through
+    the global sort: hyperedge 0 (3,000 vertices, no stored mask) owns its
+    hyperwedges in input order; a 1,501-vertex partner gives a large omega
+    and a 101-vertex one uses all four mask words."""
+    edges = [list(range(3000)), list(range(0, 3000, 2)) + [3000], list(range(100)) + [5000]]
+    edges += [[i, 3001 + (i % 50)] for i in range(3000)]
+    g = synth.from_lists(edges, 5001, "many-incidences")
+    for flags in (htri.HTRI_DEDUPE_EDGES | htri.HTRI_ORDER_INPUT, htri.HTRI_DEDUPE_EDGES):
+        check_exact(htri, g, flags=flags)
