@@ -1110,7 +1110,7 @@ struct WinArgs {
 };
 
 template <bool PER_EDGE, bool PER_WEDGE>
-__global__ __launch_bounds__(kBlock) void k_close_window(WinArgs A) {
+__global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
     __shared__ uint32_t BR[kWinWordsMax], BK[kWinClasses][kWinWordsMax];
     __shared__ int32_t PR[kWinWordsMax];
     __shared__ uint32_t cls[32 * kMaskWordsMax];
