@@ -147,11 +147,12 @@ __device__ __forceinline__ void probe_tile(const uint2 *tab, int hbits, int wbit
     bool more = false;
 #pragma unroll
     for (int u = 0; u < kUnroll; u++) {
+        // an empty slot's entry word is 0 and a probed key k << wbits never is (k > j > r >= 0)
         const uint32_t kk = e[u] & kmask;
-        const bool h0 = ((B[u].x & kmask) == kk) & (B[u].y != kEmptyPos);
-        const bool h1 = ((B[u].z & kmask) == kk) & (B[u].w != kEmptyPos);
+        const bool h0 = (B[u].x & kmask) == kk;
+        const bool h1 = (B[u].z & kmask) == kk;
         hit[u] = val[u] & (h0 | h1);
-        cont[u] = val[u] & !(h0 | h1) & (B[u].w != kEmptyPos);
+        cont[u] = val[u] & !(h0 | h1) & (B[u].z != 0u);
         more |= cont[u];
         sl[u] = h0 ? make_uint2(B[u].x, B[u].y) : make_uint2(B[u].z, B[u].w);
     }
@@ -166,9 +167,9 @@ __device__ __forceinline__ void probe_tile(const uint2 *tab, int hbits, int wbit
                 do {
                     bb = (bb + 1) & nbm1;
                     Bx = tq[bb];
-                    h0 = ((Bx.x & kmask) == kk) & (Bx.y != kEmptyPos);
-                    h1 = ((Bx.z & kmask) == kk) & (Bx.w != kEmptyPos);
-                } while (!(h0 | h1 | (Bx.w == kEmptyPos)));
+                    h0 = (Bx.x & kmask) == kk;
+                    h1 = (Bx.z & kmask) == kk;
+                } while (!(h0 | h1 | (Bx.z == 0u)));
                 hit[u] = h0 | h1;
                 sl[u] = h0 ? make_uint2(Bx.x, Bx.y) : make_uint2(Bx.z, Bx.w);
             }
@@ -179,12 +180,13 @@ __device__ __forceinline__ void probe_tile(const uint2 *tab, int hbits, int wbit
     for (int u = 0; u < kUnroll; u++) sm[u] = ent_sm[hit[u] ? sl[u].y : 0u];
     bool fast[kUnroll];
     bool slow = false;
+    uint32_t n9 = 0;
 #pragma unroll
     for (int u = 0; u < kUnroll; u++) {
         const int wik = (int)(sl[u].x & wmask), wjk = (int)(e[u] & wmask);
         fast[u] = hit[u] & ffast[u] & (wik == fwij[u]) & (wjk == fwij[u]) & (sm[u].y == fm0[u]) &
                   ((int)sm[u].x > fwij[u]);
-        c9 += fast[u];
+        n9 += fast[u];
         po[u] = 0u;
         slow |= hit[u] & !fast[u];
     }
@@ -209,15 +211,23 @@ __device__ __forceinline__ void probe_tile(const uint2 *tab, int hbits, int wbit
                 }
                 const uint32_t m7 = region_mask(si, J.sj, (int)sm[u].x, J.wij, wik, wjk, g);
                 if (m7 != kMaskCommonVertex) po[u] = lut[m7];
-                else c9++;
+                else n9++;
             }
         }
     }
+    c9 += n9;
+    if (PER_EDGE) {
+        // every pattern counted per hyperedge (the default): a hit is a counted hit
+        const bool all_patterns = (emask & 0x1FFFFEu) == 0x1FFFFEu;
 #pragma unroll
-    for (int u = 0; u < kUnroll; u++) {
-        const uint32_t p = po[u] ? po[u] : kPatternCommonVertex;
-        mhit[u] = PER_EDGE && hit[u] && ((emask >> p) & 1u);
-        if (PER_EDGE && mhit[u]) atomicAdd(&ent_ck[sl[u].y], 1u);
+        for (int u = 0; u < kUnroll; u++) {
+            const uint32_t p = po[u] ? po[u] : kPatternCommonVertex;
+            mhit[u] = hit[u] && (all_patterns || ((emask >> p) & 1u));
+            if (mhit[u]) atomicAdd(&ent_ck[sl[u].y], 1u);
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++) mhit[u] = false;
     }
 }
 
@@ -340,7 +350,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
         const uint32_t lo = gld(G.fadj + base + item.cb) >> wbits;
         const uint32_t hi = gld(G.fadj + base + item.ce - 1) >> wbits;
 
-        for (int s = tid; s < H; s += kBlock) tab[s] = make_uint2(0xFFFFFFFFu, kEmptyPos);
+        for (int s = tid; s < H; s += kBlock) tab[s] = make_uint2(0u, kEmptyPos);
         __syncthreads();
         // stage the chunk
         for (int q = tid; q < cl; q += kBlock) {
@@ -675,7 +685,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
         while ((1 << hbits) < 4 * d) hbits++;
         const int H = 1 << hbits;              // <= 4 * kWaveOwnerMax
         wave_lds_sync();                       // the previous owner's reads are done
-        for (int t = lane; t < H; t += kWave) Wl.tab[t] = make_uint2(0xFFFFFFFFu, kEmptyPos);
+        for (int t = lane; t < H; t += kWave) Wl.tab[t] = make_uint2(0u, kEmptyPos);
         wave_lds_sync();
         // lane q holds entry q of N+(r): the third hyperedge k = j_q of the
         // chunk role and the partner j_q of the wedge (r, j_q)
