@@ -517,26 +517,29 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
         } else {
             // Flattened items: the partner segments laid end to end; each step
             // a wave takes 64*kUnroll consecutive entries, kUnroll per lane.
+            // here total < nseg * 256 <= 65536: stream offsets fit in 32 bits
+            const int total32 = (int)total;
             int qa = -1;                   // address cursor
-            int64_t qa_end = 0, srca = 0;
+            int qa_end = 0;
+            int64_t srca = 0;
             int q = -1;                    // segment whose counters this lane holds
             uint32_t cj = 0, cjm = 0;
-            const int64_t stride = (int64_t)kBlock * kUnroll;
-            auto fetch = [&](int64_t f0, uint32_t *ent, int *segu) {
+            const int stride = kBlock * kUnroll;
+            auto fetch = [&](int f0, uint32_t *ent, int *segu) {
 #pragma unroll
                 for (int u = 0; u < kUnroll; u++) {
-                    const int64_t f = f0 + u;
+                    const int f = f0 + u;
                     segu[u] = -1;
                     int64_t addr = 0;
-                    if (f < total) {
+                    if (f < total32) {
                         if (f >= qa_end) {
                             int lo_s = qa < 0 ? 0 : qa + 1, hi_s = nseg;
                             while (lo_s < hi_s) {
                                 int mid = (lo_s + hi_s) >> 1;
-                                if (seg_pre[mid + 1] <= f) lo_s = mid + 1; else hi_s = mid;
+                                if ((int)seg_pre[mid + 1] <= f) lo_s = mid + 1; else hi_s = mid;
                             }
                             qa = lo_s;
-                            qa_end = seg_pre[qa + 1];
+                            qa_end = (int)seg_pre[qa + 1];
                             srca = seg_src[qa] - seg_pre[qa];
                         }
                         segu[u] = qa;
@@ -545,16 +548,16 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                     ent[u] = segu[u] >= 0 ? gld(G.fadj + addr) : 0u;
                 }
             };
-            int64_t fb = (int64_t)wave * kWave * kUnroll;
+            int fb = wave * kWave * kUnroll;
             uint32_t entA[kUnroll];
             int seguA[kUnroll];
-            if (fb < total) fetch(fb + (int64_t)lane * kUnroll, entA, seguA);
-            for (; fb < total; fb += stride) {
+            if (fb < total32) fetch(fb + lane * kUnroll, entA, seguA);
+            for (; fb < total32; fb += stride) {
                 uint32_t entB[kUnroll];
                 int seguB[kUnroll];
-                const int64_t fbn = fb + stride;
-                if (fbn < total) {
-                    fetch(fbn + (int64_t)lane * kUnroll, entB, seguB);
+                const int fbn = fb + stride;
+                if (fbn < total32) {
+                    fetch(fbn + lane * kUnroll, entB, seguB);
                 } else {
 #pragma unroll
                     for (int u = 0; u < kUnroll; u++) {
@@ -725,15 +728,16 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
         int qa = 0;                            // search cursor (monotone per lane)
         int q = -1;                            // segment whose counters this lane holds
         uint32_t cj = 0, cjm = 0;
-        for (int64_t fb = 0; fb < total; fb += (int64_t)kWave * kUnroll) {
+        const int wtotal = (int)total;          // <= kWaveStreamMax
+        for (int fb = 0; fb < wtotal; fb += kWave * kUnroll) {
             uint32_t ent4[kUnroll];
             int seg4[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; u++) {
-                const int64_t f = fb + (int64_t)lane * kUnroll + u;
+                const int f = fb + lane * kUnroll + u;
                 seg4[u] = -1;
                 ent4[u] = 0u;
-                if (f < total) {
+                if (f < wtotal) {
                     while (Wl.incl[qa] <= f) qa++;     // ends at a segment <= d-2 since f < total
                     seg4[u] = qa;
                     ent4[u] = gld(G.fadj + Wl.src[qa] + f);
