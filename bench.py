@@ -281,6 +281,15 @@ def main() -> int:
         f"reduce, window part, probing part) ms {np.round(stage_ms.mean(axis=0), 2).tolist()}; "
         f"closure stats {cstats.tolist()}")
 
+    # patterns 1-8 alone, searched around the inclusion hyperwedges
+    incl_ms = []
+    for _ in range(3):
+        ci, _, _ = G.count_patterns(per_edge=True, device_out=True, window="inclusion_classes")
+        t4 = G.last_timings()
+        incl_ms.append(float(t4[1] + t4[2]))
+    assert np.array_equal(ci[1:9], counts[1:9]), "inclusion-class counts differ from the full count"
+    log(f"[bench] patterns 1-8 around the {int(s[2])} inclusion hyperwedges: {np.median(incl_ms):.2f} ms")
+
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on an owner sample ...")
@@ -344,6 +353,13 @@ def main() -> int:
             "ms": win_ms,
             "achieved_GBps": BW / (win_ms / 1e3) / 1e9 if win_ms > 0 else None,
             "hits_enumerated": int(cstats[11]),
+        },
+        "inclusion_classes": {
+            "what": "patterns 1-8 (classes CCC, TCC, TTC) with per-hyperedge counts, searched around the "
+                    "inclusion hyperwedges only; equal to the full count's",
+            "inclusion_hyperwedges": int(s[2]),
+            "ms": float(np.median(incl_ms)),
+            "full_closure_ms": close_ms,
         },
         "cpu_baseline": cpu,
         "estimator": study,

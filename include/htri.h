@@ -95,6 +95,9 @@ typedef struct {
 #define HTRI_COUNT_NO_WINDOW 16u     /* close every owner by probing           */
 #define HTRI_COUNT_WINDOW_ALWAYS 32u /* use the dense window whenever it holds */
                                      /* a hyperwedge (else: when dense enough) */
+#define HTRI_COUNT_INCLUSION_CLASSES 64u /* count only patterns 1-8 (classes    */
+                                         /* CCC, TCC, TTC), around the inclusion */
+                                         /* hyperwedges; per_wedge must be NULL  */
 
 /* Load and normalise a hypergraph (Def. 2.1 and the distinct-hyperedge
  * assumption of Section 2), build E_v (Algorithm 2).
@@ -154,7 +157,13 @@ htri_status htri_get_wedges(const htri_graph *g, int32_t *src, int32_t *dst, int
  *               order), the number of third hyperedges that close it and
  *               come after dst in prec (all patterns).
  *   out_flags   HTRI_OUTPUT_ON_DEVICE, and at most one of
- *               HTRI_COUNT_NO_WINDOW / HTRI_COUNT_WINDOW_ALWAYS.  By default
+ *               HTRI_COUNT_NO_WINDOW / HTRI_COUNT_WINDOW_ALWAYS /
+ *               HTRI_COUNT_INCLUSION_CLASSES.  The last counts only the
+ *               classes whose hyper-triangles hold an inclusion hyperwedge
+ *               (patterns 1-8; Count-CCC, Count-TCC and Count-TTC of
+ *               Section 3.1 search only around those hyperwedges): counts[p]
+ *               for p > 8 are 0, per_edge counts the masked triangles of
+ *               patterns 1-8.  By default
  *               the owners of the top ranks (up to 16384 of them) are closed
  *               by bitmap intersection when the hyperwedges among them are
  *               dense (at least 1/16 of all pairs); the counts do not

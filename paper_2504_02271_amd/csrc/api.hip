@@ -191,8 +191,14 @@ htri_status htri_get_wedges(const htri_graph *hc, int32_t *src, int32_t *dst, in
 htri_status htri_count_patterns(htri_graph *h, uint32_t per_edge_pattern_mask, int64_t counts[21],
                                 int64_t *per_edge, int32_t *per_wedge, uint32_t out_flags) {
     if (!h || !counts) return HTRI_E_INVALID;
-    if (out_flags & ~(HTRI_OUTPUT_ON_DEVICE | HTRI_COUNT_NO_WINDOW | HTRI_COUNT_WINDOW_ALWAYS)) return HTRI_E_INVALID;
-    if ((out_flags & HTRI_COUNT_NO_WINDOW) && (out_flags & HTRI_COUNT_WINDOW_ALWAYS)) return HTRI_E_INVALID;
+    if (out_flags & ~(HTRI_OUTPUT_ON_DEVICE | HTRI_COUNT_NO_WINDOW | HTRI_COUNT_WINDOW_ALWAYS |
+                      HTRI_COUNT_INCLUSION_CLASSES))
+        return HTRI_E_INVALID;
+    {
+        const uint32_t modes = out_flags & (HTRI_COUNT_NO_WINDOW | HTRI_COUNT_WINDOW_ALWAYS | HTRI_COUNT_INCLUSION_CLASSES);
+        if (modes & (modes - 1)) return HTRI_E_INVALID;        // at most one mode
+    }
+    if ((out_flags & HTRI_COUNT_INCLUSION_CLASSES) && per_wedge) return HTRI_E_INVALID;
     if (!h->g.have_wedges) {
         h->g.err = "htri_build_wedges has not run";
         return HTRI_E_STATE;
@@ -214,7 +220,8 @@ htri_status htri_count_patterns(htri_graph *h, uint32_t per_edge_pattern_mask, i
             else { cw_tmp.alloc(g.al, g.nw); cw_dev = cw_tmp.p; }
         }
         int64_t c[21];
-        htri::count_patterns(g, mask, out_flags, c, t_dev, cw_dev);
+        if (out_flags & HTRI_COUNT_INCLUSION_CLASSES) htri::count_inclusion_classes(g, mask, c, t_dev);
+        else htri::count_patterns(g, mask, out_flags, c, t_dev, cw_dev);
         if (per_edge && !dev && g.m)
             HTRI_HIP(hipMemcpyAsync(per_edge, t_dev, sizeof(int64_t) * g.m, hipMemcpyDeviceToHost, g.stream));
         if (per_wedge && !dev && g.nw)

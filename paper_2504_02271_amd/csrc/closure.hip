@@ -1407,6 +1407,170 @@ void close_window(Graph &g, const WindowPlan &w, uint32_t emask, const uint8_t *
     HTRI_HIP(hipStreamSynchronize(s));
 }
 
+// ---------------------------------------------------------------- inclusion classes
+
+namespace {
+
+// Every hyper-triangle of the classes CCC, TCC and TTC (patterns 1-8) holds
+// at least one inclusion hyperwedge (Def. 2.3), and those are few, so these
+// classes are counted by searching around the inclusion hyperwedges only
+// (the approach of Count-CCC, Count-TCC and Count-TTC, Section 3.1).  For an
+// inclusion hyperwedge e_s < e_L (e_s a proper subset of e_L) the third
+// hyperedges are the other hyperedges meeting e_s (a vertex of e_s is a
+// vertex of e_L), with omega_sk = |e_s & e_k| = g and omega_Lk from a
+// merge of member lists.  A triangle with several inclusion hyperwedges is
+// counted at the least of them (pairs ordered by (smaller rank, larger rank));
+// a candidate k is taken once, at its smallest common vertex with e_s.
+
+// inclusion hyperwedges as (owner, partner) rank pairs; one wave per owner
+__global__ void k_incl_pairs(const int64_t *fptr, const uint32_t *fadj, const int32_t *esize, int64_t m, int wbits,
+                             unsigned long long *n, int2 *pairs) {
+    const uint32_t wmask = (1u << wbits) - 1;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; r < m; r += nwaves) {
+        const int32_t sr = esize[r];
+        for (int64_t e = fptr[r] + lane; e < fptr[r + 1]; e += kWave) {
+            const uint32_t ent = fadj[e];
+            const int32_t j = (int32_t)(ent >> wbits);
+            const int32_t sj = esize[j];
+            if ((int32_t)(ent & wmask) == (sr < sj ? sr : sj)) {
+                const unsigned long long at = atomicAdd(n, 1ull);
+                pairs[at] = make_int2((int32_t)r, j);
+            }
+        }
+    }
+}
+
+// |e_a & e_b| of two sorted member lists, and their smallest common vertex (or -1)
+__device__ __forceinline__ int common_members(const int64_t *eptr, const int32_t *emem, int32_t a, int32_t b,
+                                              int32_t &first) {
+    int64_t x = eptr[a], xe = eptr[a + 1], y = eptr[b], ye = eptr[b + 1];
+    int c = 0;
+    first = -1;
+    while (x < xe && y < ye) {
+        const int32_t u = emem[x], v = emem[y];
+        if (u < v) x++;
+        else if (v < u) y++;
+        else {
+            if (c == 0) first = u;
+            c++;
+            x++;
+            y++;
+        }
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint64_t pair_key(int32_t a, int32_t b) {
+    const uint32_t lo = (uint32_t)(a < b ? a : b), hi = (uint32_t)(a < b ? b : a);
+    return ((uint64_t)lo << 32) | hi;
+}
+
+// one block per inclusion hyperwedge
+__global__ __launch_bounds__(kBlock) void k_incl_count(const int2 *pairs, const int64_t *eptr, const int32_t *emem,
+                                                       const int32_t *esize, const int64_t *vptr,
+                                                       const int32_t *vadj, const uint8_t *lut_g, uint32_t emask,
+                                                       unsigned long long *counts, unsigned long long *t) {
+    __shared__ unsigned long long cnt[21];
+    __shared__ uint8_t lut[128];
+    const int tid = threadIdx.x;
+    if (tid < 21) cnt[tid] = 0ull;
+    if (tid < 128) lut[tid] = lut_g[tid];
+    __syncthreads();
+    const int2 pr = pairs[blockIdx.x];
+    const bool first_small = esize[pr.x] < esize[pr.y];
+    const int32_t sv = first_small ? pr.x : pr.y, Lv = first_small ? pr.y : pr.x;   // e_s inside e_L
+    const int ss = esize[sv], sL = esize[Lv];
+    const uint64_t key_sL = pair_key(sv, Lv);
+    for (int64_t q = eptr[sv]; q < eptr[sv + 1]; q++) {
+        const int32_t v = emem[q];
+        for (int64_t x = vptr[v] + tid; x < vptr[v + 1]; x += kBlock) {
+            const int32_t k = vadj[x];
+            if (k == sv || k == Lv) continue;
+            int32_t first;
+            const int wsk = common_members(eptr, emem, sv, k, first);
+            if (first != v) continue;                       // k is taken at its smallest common vertex
+            int32_t f2;
+            const int wLk = common_members(eptr, emem, Lv, k, f2);
+            const int sk = esize[k];
+            // count at the least inclusion hyperwedge of the triangle
+            if (wsk == (ss < sk ? ss : sk) && pair_key(sv, k) < key_sL) continue;
+            if (wLk == (sL < sk ? sL : sk) && pair_key(Lv, k) < key_sL) continue;
+            const uint32_t p = lut[region_mask(ss, sL, sk, ss, wsk, wLk, wsk)];
+            atomicAdd(&cnt[p], 1ull);
+            if (t && ((emask >> p) & 1u)) {
+                atomicAdd(&t[sv], 1ull);
+                atomicAdd(&t[Lv], 1ull);
+                atomicAdd(&t[k], 1ull);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid >= 1 && tid < 21 && cnt[tid]) atomicAdd(&counts[tid], cnt[tid]);
+}
+
+}  // namespace
+
+void count_inclusion_classes(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev) {
+    hipStream_t s = g.stream;
+    Allocator &A = g.al;
+    const int64_t m = g.m;
+    hipEvent_t e0, e1, e2;
+    HTRI_HIP(hipEventCreate(&e0));
+    HTRI_HIP(hipEventCreate(&e1));
+    HTRI_HIP(hipEventCreate(&e2));
+    HTRI_HIP(hipEventRecord(e0, s));
+    const int64_t nc = g.summary[2];                  // inclusion hyperwedges (step 1)
+    DBuf<int2> pairs(A, nc);
+    DBuf<unsigned long long> ctr(A, 22);              // [0] pair count, [1..21] pattern counts
+    DBuf<uint8_t> lut(A, 128);
+    fill_u64((uint64_t *)ctr.p, 22, 0, s);
+    HTRI_HIP(hipMemcpyAsync(lut.p, pattern_lut(), 128, hipMemcpyHostToDevice, s));
+    DBuf<unsigned long long> t;
+    if (t_dev) {
+        t.alloc(A, m);
+        fill_u64((uint64_t *)t.p, m, 0, s);
+    }
+    if (m > 0 && nc > 0) {
+        hipLaunchKernelGGL(k_incl_pairs, dim3(grid_for(m * kWave, 256, 8192)), dim3(256), 0, s, g.fptr.p, g.fadj.p,
+                           g.esize.p, m, g.wbits, ctr.p, pairs.p);
+        HTRI_LAUNCH_CHECK();
+    }
+    HTRI_HIP(hipEventRecord(e1, s));
+    unsigned long long found = 0;
+    HTRI_HIP(hipMemcpyAsync(&found, ctr.p, sizeof(found), hipMemcpyDeviceToHost, s));
+    HTRI_HIP(hipStreamSynchronize(s));
+    if ((int64_t)found != nc) fail(HTRI_E_DEVICE, "inclusion hyperwedge count differs from step 1");
+    if (nc > 0) {
+        hipLaunchKernelGGL(k_incl_count, dim3((unsigned)nc), dim3(kBlock), 0, s, pairs.p, g.eptr.p, g.emem.p,
+                           g.esize.p, g.vptr.p, g.vadj.p, lut.p, mask, ctr.p + 1, t_dev ? t.p : nullptr);
+        HTRI_LAUNCH_CHECK();
+    }
+    HTRI_HIP(hipEventRecord(e2, s));
+    if (t_dev && m > 0) {
+        hipLaunchKernelGGL(k_rank_to_norm_u64, dim3(grid_for(m, 256)), dim3(256), 0, s, t.p, g.norm_of_rank.p, m,
+                           (int64_t *)t_dev);
+        HTRI_LAUNCH_CHECK();
+    }
+    unsigned long long hc[22];
+    HTRI_HIP(hipMemcpyAsync(hc, ctr.p, sizeof(hc), hipMemcpyDeviceToHost, s));
+    HTRI_HIP(hipStreamSynchronize(s));
+    counts[0] = 0;
+    for (int p = 1; p <= 20; p++) {
+        counts[p] = p <= 8 ? (int64_t)hc[1 + p] : 0;
+        counts[0] += counts[p];
+    }
+    g.tm.schedule_ms = 0;
+    HTRI_HIP(hipEventElapsedTime(&g.tm.schedule_ms, e0, e1));
+    HTRI_HIP(hipEventElapsedTime(&g.tm.closure_ms, e1, e2));
+    g.tm.reduce_ms = g.tm.window_ms = 0;
+    g.tm.probe_ms = g.tm.closure_ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+}
+
 // ---------------------------------------------------------------- LUT
 
 namespace {

@@ -242,6 +242,8 @@ void close_window(Graph &g, const WindowPlan &w, uint32_t emask, const uint8_t *
 int close_blocks_per_cu(const CloseConfig &cfg, bool pe, bool pw);
 void launch_close_kernel(const CloseConfig &cfg, bool pe, bool pw, const CloseArgs &a, int nblocks, hipStream_t s);
 bool valid_config(const CloseConfig &cfg);
+// patterns 1-8 only, by searching around the inclusion hyperwedges
+void count_inclusion_classes(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev /*m or null*/);
 void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21], uint64_t *t_dev /*m or null*/,
                     uint32_t *cw_dev /*nw or null*/);
 // sample.hip: closure of explicit wedges (per-sample counts) and weighted

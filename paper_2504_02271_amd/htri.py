@@ -22,7 +22,9 @@ HTRI_OUTPUT_ON_DEVICE = 4
 HTRI_ORDER_INPUT = 8
 HTRI_COUNT_NO_WINDOW = 16
 HTRI_COUNT_WINDOW_ALWAYS = 32
-_WINDOW_FLAGS = {"auto": 0, "off": HTRI_COUNT_NO_WINDOW, "always": HTRI_COUNT_WINDOW_ALWAYS}
+HTRI_COUNT_INCLUSION_CLASSES = 64
+_WINDOW_FLAGS = {"auto": 0, "off": HTRI_COUNT_NO_WINDOW, "always": HTRI_COUNT_WINDOW_ALWAYS,
+                 "inclusion_classes": HTRI_COUNT_INCLUSION_CLASSES}
 HTRI_MODEL_NUM_PARAMS = 5313
 ALL_PATTERNS = 0x1FFFFE
 
@@ -245,7 +247,9 @@ class Graph:
                        device_out: bool = False, window: str = "auto"):
         """Returns (counts int64[21], per_edge or None, per_wedge or None).
         With device_out the per-edge/per-wedge results are torch tensors on the GPU.
-        window: "auto" (dense top-rank window when it pays), "off", "always"."""
+        window: "auto" (dense top-rank window when it pays), "off", "always", or
+        "inclusion_classes" (patterns 1-8 only, searched around the inclusion
+        hyperwedges; no per_wedge)."""
         counts = np.zeros(21, np.int64)
         pe = pw = None
         flags = _WINDOW_FLAGS[window]

@@ -73,6 +73,12 @@ def check_exact(htri, g, flags=None, wedge_sample=None, nthreads=0, seed=0, wind
         assert np.array_equal(pe, r.t), win
         assert int(pw.astype(np.int64).sum()) == int(counts[0])
         assert np.array_equal(pw[idx].astype(np.int64), want), win
+    # classes with an inclusion hyperwedge only (patterns 1-8), searched around those hyperwedges
+    incl_mask = 0x1FE
+    ci, pei, _ = G.count_patterns(mask=incl_mask, per_edge=True, window="inclusion_classes")
+    ri = o.count(nthreads=nthreads, edge_mask=incl_mask)
+    assert np.array_equal(ci[1:9], r.H[1:9]) and (ci[9:] == 0).all() and ci[0] == r.H[1:9].sum(), (ci, r.H)
+    assert np.array_equal(pei, ri.t)
     return G, o, counts
 
 
@@ -183,6 +189,10 @@ def test_errors(htri):
     with pytest.raises(htri.HtriError) as e:
         G.count_patterns()
     assert e.value.code == -8
+    G.build_wedges()
+    with pytest.raises(htri.HtriError) as e:
+        G.count_patterns(per_wedge=True, window="inclusion_classes")
+    assert e.value.code == -1
 
 
 def test_pattern_mask_for_per_edge_counts(htri):
@@ -196,6 +206,9 @@ def test_pattern_mask_for_per_edge_counts(htri):
             counts, pe, _ = G.count_patterns(mask=mask, per_edge=True, window=win)
             assert np.array_equal(counts, r.H), (mask, win)
             assert np.array_equal(pe, r.t), (mask, win)
+        ci, pei, _ = G.count_patterns(mask=mask, per_edge=True, window="inclusion_classes")
+        assert np.array_equal(ci[1:9], r.H[1:9])
+        assert np.array_equal(pei, o.count(edge_mask=mask & 0x1FE).t), mask
 
 
 def test_device_input_and_output(htri):
