@@ -173,6 +173,19 @@ htri_status htri_get_wedges(const htri_graph *g, int32_t *src, int32_t *dst, int
 htri_status htri_count_patterns(htri_graph *g, uint32_t per_edge_pattern_mask, int64_t counts[21],
                                 int64_t *per_edge, int32_t *per_wedge, uint32_t out_flags);
 
+/* List the hyper-triangles of one pattern (the enumeration half of the
+ * problem statement, Section 2): pattern 1..20; out receives up to capacity
+ * triples of normalised hyperedge ids, each sorted ascending, in no fixed
+ * order (host array int32[3*capacity], or device with HTRI_OUTPUT_ON_DEVICE
+ * in out_flags); found = the number of hyper-triangles of the pattern, which
+ * may exceed capacity (then an unspecified capacity of them are written).
+ * Patterns 1-8 are searched around the inclusion hyperwedges; the others by
+ * closing every hyperwedge.
+ * Errors: HTRI_E_INVALID, HTRI_E_STATE (no wedges yet), HTRI_E_OOM,
+ * HTRI_E_DEVICE. */
+htri_status htri_enumerate(htri_graph *g, int32_t pattern, int64_t capacity, int32_t *out, int64_t *found,
+                           uint32_t out_flags);
+
 /* Device time of the stages of the last htri_build_wedges +
  * htri_count_patterns, milliseconds: [0] wedge build, [1] schedule,
  * [2] closure (window and probing), [3] reduce, [4] the dense window

@@ -135,6 +135,23 @@ def count(edges: Sequence[Iterable[int]]):
     return H, t
 
 
+def triangles(edges: Sequence[Iterable[int]]):
+    """Pattern -> sorted list of hyper-triangles (i, j, k), i < j < k, over the
+    normalised ids, by the same triple loop as count()."""
+    E = normalise(edges)
+    m = len(E)
+    out = {p: [] for p in range(1, 21)}
+    adj = [[bool(E[x] & E[y]) for y in range(m)] for x in range(m)]
+    for i in range(m):
+        for j in range(i + 1, m):
+            if not adj[i][j]:
+                continue
+            for k in range(j + 1, m):
+                if adj[i][k] and adj[j][k]:
+                    out[pattern_of(E[i], E[j], E[k])].append((i, j, k))
+    return out
+
+
 def hyperwedges(edges: Sequence[Iterable[int]]):
     """Sorted list of (i, j, omega_ij, is_inclusion) over normalised ids, i<j."""
     E = normalise(edges)

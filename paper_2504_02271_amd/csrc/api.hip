@@ -1,6 +1,8 @@
 // C ABI of libhtri: argument checks, status codes, host <-> device copies.
 #include <mutex>
 
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace {
@@ -153,6 +155,42 @@ htri_status htri_clear_wedges(htri_graph *h) {
         g.indeg.reset();
         g.nw = 0;
         g.have_wedges = false;
+    });
+}
+
+htri_status htri_enumerate(htri_graph *h, int32_t pattern, int64_t capacity, int32_t *out, int64_t *found,
+                           uint32_t out_flags) {
+    if (!h || !found || pattern < 1 || pattern > 20 || capacity < 0 || (capacity > 0 && !out)) return HTRI_E_INVALID;
+    if (out_flags & ~HTRI_OUTPUT_ON_DEVICE) return HTRI_E_INVALID;
+    if (!h->g.have_wedges) {
+        h->g.err = "htri_build_wedges has not run";
+        return HTRI_E_STATE;
+    }
+    return run(&h->g, [&] {
+        htri::Graph &g = h->g;
+        const bool dev = out_flags & HTRI_OUTPUT_ON_DEVICE;
+        htri::DBuf<int32_t> tmp;
+        int32_t *dout = out;
+        if (!dev && capacity > 0) {
+            tmp.alloc(g.al, capacity * 3);
+            dout = tmp.p;
+        }
+        htri::DBuf<unsigned long long> cnt(g.al, 1);
+        htri::fill_u64((uint64_t *)cnt.p, 1, 0, g.stream);
+        if (pattern <= 8) {
+            int64_t c[21];
+            htri::count_inclusion_classes(g, 0x1FFFFEu, c, nullptr, pattern, capacity, dout, cnt.p);
+        } else {
+            htri::enumerate_all_wedges(g, pattern, capacity, dout, cnt.p);
+        }
+        unsigned long long n = 0;
+        HTRI_HIP(hipMemcpyAsync(&n, cnt.p, sizeof(n), hipMemcpyDeviceToHost, g.stream));
+        HTRI_HIP(hipStreamSynchronize(g.stream));
+        *found = (int64_t)n;
+        const int64_t w = std::min<int64_t>((int64_t)n, capacity);
+        if (!dev && w > 0)
+            HTRI_HIP(hipMemcpyAsync(out, dout, sizeof(int32_t) * 3 * w, hipMemcpyDeviceToHost, g.stream));
+        HTRI_HIP(hipStreamSynchronize(g.stream));
     });
 }
 

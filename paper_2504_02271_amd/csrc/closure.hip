@@ -1468,10 +1468,14 @@ __device__ __forceinline__ uint64_t pair_key(int32_t a, int32_t b) {
 }
 
 // one block per inclusion hyperwedge
+// (with out: the triangles of pattern `target` written as sorted triples of
+// normalised ids while room lasts, found counting them all)
 __global__ __launch_bounds__(kBlock) void k_incl_count(const int2 *pairs, const int64_t *eptr, const int32_t *emem,
                                                        const int32_t *esize, const int64_t *vptr,
                                                        const int32_t *vadj, const uint8_t *lut_g, uint32_t emask,
-                                                       unsigned long long *counts, unsigned long long *t) {
+                                                       unsigned long long *counts, unsigned long long *t,
+                                                       int target, const int32_t *norm_of_rank, int64_t capacity,
+                                                       int32_t *out, unsigned long long *found) {
     __shared__ unsigned long long cnt[21];
     __shared__ uint8_t lut[128];
     const int tid = threadIdx.x;
@@ -1499,6 +1503,18 @@ __global__ __launch_bounds__(kBlock) void k_incl_count(const int2 *pairs, const 
             if (wLk == (sL < sk ? sL : sk) && pair_key(Lv, k) < key_sL) continue;
             const uint32_t p = lut[region_mask(ss, sL, sk, ss, wsk, wLk, wsk)];
             atomicAdd(&cnt[p], 1ull);
+            if (out && (int)p == target) {
+                const unsigned long long at = atomicAdd(found, 1ull);
+                if ((int64_t)at < capacity) {
+                    int32_t a = norm_of_rank[sv], b = norm_of_rank[Lv], c = norm_of_rank[k];
+                    if (a > b) { const int32_t x = a; a = b; b = x; }
+                    if (b > c) { const int32_t x = b; b = c; c = x; }
+                    if (a > b) { const int32_t x = a; a = b; b = x; }
+                    out[at * 3 + 0] = a;
+                    out[at * 3 + 1] = b;
+                    out[at * 3 + 2] = c;
+                }
+            }
             if (t && ((emask >> p) & 1u)) {
                 atomicAdd(&t[sv], 1ull);
                 atomicAdd(&t[Lv], 1ull);
@@ -1512,7 +1528,8 @@ __global__ __launch_bounds__(kBlock) void k_incl_count(const int2 *pairs, const 
 
 }  // namespace
 
-void count_inclusion_classes(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev) {
+void count_inclusion_classes(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev, int target,
+                             int64_t capacity, int32_t *dev_out, unsigned long long *dev_found) {
     hipStream_t s = g.stream;
     Allocator &A = g.al;
     const int64_t m = g.m;
@@ -1544,7 +1561,8 @@ void count_inclusion_classes(Graph &g, uint32_t mask, int64_t counts[21], uint64
     if ((int64_t)found != nc) fail(HTRI_E_DEVICE, "inclusion hyperwedge count differs from step 1");
     if (nc > 0) {
         hipLaunchKernelGGL(k_incl_count, dim3((unsigned)nc), dim3(kBlock), 0, s, pairs.p, g.eptr.p, g.emem.p,
-                           g.esize.p, g.vptr.p, g.vadj.p, lut.p, mask, ctr.p + 1, t_dev ? t.p : nullptr);
+                           g.esize.p, g.vptr.p, g.vadj.p, lut.p, mask, ctr.p + 1, t_dev ? t.p : nullptr, target,
+                           g.norm_of_rank.p, capacity, dev_out, dev_found);
         HTRI_LAUNCH_CHECK();
     }
     HTRI_HIP(hipEventRecord(e2, s));

@@ -242,8 +242,13 @@ void close_window(Graph &g, const WindowPlan &w, uint32_t emask, const uint8_t *
 int close_blocks_per_cu(const CloseConfig &cfg, bool pe, bool pw);
 void launch_close_kernel(const CloseConfig &cfg, bool pe, bool pw, const CloseArgs &a, int nblocks, hipStream_t s);
 bool valid_config(const CloseConfig &cfg);
-// patterns 1-8 only, by searching around the inclusion hyperwedges
-void count_inclusion_classes(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev /*m or null*/);
+// patterns 1-8 only, by searching around the inclusion hyperwedges; with
+// dev_out, also the triangles of pattern target (sorted normalised triples)
+void count_inclusion_classes(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev /*m or null*/,
+                             int target = 0, int64_t capacity = 0, int32_t *dev_out = nullptr,
+                             unsigned long long *dev_found = nullptr);
+// every hyperwedge closed, the triangles of pattern target listed
+void enumerate_all_wedges(Graph &g, int target, int64_t capacity, int32_t *dev_out, unsigned long long *dev_found);
 void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21], uint64_t *t_dev /*m or null*/,
                     uint32_t *cw_dev /*nw or null*/);
 // sample.hip: closure of explicit wedges (per-sample counts) and weighted

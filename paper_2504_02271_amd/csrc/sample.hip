@@ -89,7 +89,10 @@ __device__ __forceinline__ int64_t owner_of(const int64_t *fptr, int64_t m, int6
 // Close wedge e (global index into the forward adjacency).  Returns, in lane
 // p (1..20), the number of closing third hyperedges of pattern p and, in lane
 // 0, their total; other lanes return 0.
-__device__ long long wave_close(const SampleArgs &A, const uint8_t *lut, int64_t e) {
+// on_hit(r, j, k, pattern) is called by each lane that finds a third
+// hyperedge k (ranks).
+template <typename OnHit>
+__device__ long long wave_close_f(const SampleArgs &A, const uint8_t *lut, int64_t e, const OnHit &on_hit) {
     const int lane = __lane_id();
     const uint32_t wmask = (1u << A.wbits) - 1;
     const int64_t r = owner_of(A.fptr, A.m, e);
@@ -143,6 +146,7 @@ __device__ long long wave_close(const SampleArgs &A, const uint8_t *lut, int64_t
                 g = triple_common_s(A.eptr, A.emem, (int32_t)r, (int32_t)j, (int32_t)k);
             }
             pat = lut[region_mask_s(si, sj, sk, wrj, wrk, wjk, g)];
+            on_hit((int32_t)r, (int32_t)j, (int32_t)k, pat);
         }
         uint64_t pend = __ballot(hit);
         if (lane == 0) cnt += __popcll(pend);
@@ -162,6 +166,37 @@ __device__ long long wave_close(const SampleArgs &A, const uint8_t *lut, int64_t
         if (bmax <= amax) b0 += kWave;
     }
     return cnt;
+}
+
+__device__ __forceinline__ long long wave_close(const SampleArgs &A, const uint8_t *lut, int64_t e) {
+    return wave_close_f(A, lut, e, [](int32_t, int32_t, int32_t, int) {});
+}
+
+// Every hyperwedge closed by one wave; the hyper-triangles of pattern
+// `target` are written as sorted triples of normalised ids while room lasts
+// (found counts them all).
+__global__ __launch_bounds__(kBlock) void k_enumerate(SampleArgs A, int target, const int32_t *norm_of_rank,
+                                                      int64_t capacity, int32_t *out,
+                                                      unsigned long long *found) {
+    __shared__ uint8_t lut[128];
+    if (threadIdx.x < 128) lut[threadIdx.x] = A.lut[threadIdx.x];
+    __syncthreads();
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    auto emit = [&](int32_t r, int32_t j, int32_t k, int pat) {
+        if (pat != target) return;
+        const unsigned long long at = atomicAdd(found, 1ull);
+        if ((int64_t)at < capacity) {
+            int32_t a = norm_of_rank[r], b = norm_of_rank[j], c = norm_of_rank[k];
+            if (a > b) { const int32_t x = a; a = b; b = x; }
+            if (b > c) { const int32_t x = b; b = c; c = x; }
+            if (a > b) { const int32_t x = a; a = b; b = x; }
+            out[at * 3 + 0] = a;
+            out[at * 3 + 1] = b;
+            out[at * 3 + 2] = c;
+        }
+    };
+    for (int64_t e = wave; e < A.nw; e += nwaves) (void)wave_close_f(A, lut, e, emit);
 }
 
 template <int MODE>
@@ -265,6 +300,19 @@ void close_wedge_list_counts(Graph &g, const int64_t *dev_idx, int64_t n, int64_
     a.out_counts = dev_out;
     int grid = (int)std::min<int64_t>(sample_grid(), (n + kWavesPerBlock - 1) / kWavesPerBlock);
     hipLaunchKernelGGL(k_sample_close<0>, dim3(std::max(grid, 1)), dim3(kBlock), 0, s, a);
+    HTRI_LAUNCH_CHECK();
+    HTRI_HIP(hipStreamSynchronize(s));
+}
+
+void enumerate_all_wedges(Graph &g, int target, int64_t capacity, int32_t *dev_out, unsigned long long *dev_found) {
+    if (g.nw <= 0) return;
+    hipStream_t s = g.stream;
+    DBuf<uint8_t> lut(g.al, 128);
+    HTRI_HIP(hipMemcpyAsync(lut.p, pattern_lut(), 128, hipMemcpyHostToDevice, s));
+    SampleArgs a = base_args(g, lut.p);
+    const int grid = (int)std::min<int64_t>(sample_grid(), (g.nw + kWavesPerBlock - 1) / kWavesPerBlock);
+    hipLaunchKernelGGL(k_enumerate, dim3(std::max(grid, 1)), dim3(kBlock), 0, s, a, target, g.norm_of_rank.p,
+                       capacity, dev_out, dev_found);
     HTRI_LAUNCH_CHECK();
     HTRI_HIP(hipStreamSynchronize(s));
 }

@@ -96,6 +96,7 @@ def load_library() -> ctypes.CDLL:
         "htri_last_timings": ([_P, _P], ctypes.c_int),
         "htri_clear_wedges": ([_P], ctypes.c_int),
         "htri_closure_stats": ([_P, _P], ctypes.c_int),
+        "htri_enumerate": ([_P, _i32, _i64, _P, _P, _u32], ctypes.c_int),
         "htri_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "htri_last_error": ([_P], ctypes.c_char_p),
         "htri_graph_free": ([_P], None),
@@ -272,6 +273,15 @@ class Graph:
         _check(self._lib.htri_count_patterns(self._h, mask, _ptr(counts), pe_p, pw_p, flags),
                "htri_count_patterns", self._h)
         return counts, pe, pw
+
+    def enumerate(self, pattern: int, capacity: int = 1 << 20):
+        """(triples int32 [min(found, capacity), 3] of normalised ids, found)."""
+        capacity = int(capacity)
+        out = np.zeros((max(capacity, 1), 3), np.int32)
+        found = ctypes.c_int64(0)
+        _check(self._lib.htri_enumerate(self._h, int(pattern), capacity, _ptr(out), ctypes.byref(found), 0),
+               "htri_enumerate", self._h)
+        return out[: min(found.value, capacity)], int(found.value)
 
     def clear_wedges(self) -> None:
         _check(self._lib.htri_clear_wedges(self._h), "htri_clear_wedges", self._h)

@@ -272,3 +272,16 @@ def test_empty_hypergraph():
     r = o.count(nthreads=1)
     assert o.m == 0 and (r.H == 0).all()
     assert o.summary().tolist() == [0, 0, 0, 0, 0, 0]
+
+
+def test_brute_triangle_listing_agrees_with_its_count():
+    """The listing used to check enumeration holds every counted triangle
+    once, under the pattern the count gives it."""
+    from oracle import brute
+    rng = np.random.default_rng(11)
+    edges = [sorted(rng.choice(30, size=int(rng.integers(1, 6)), replace=False).tolist()) for _ in range(45)]
+    H, _ = brute.count(edges)
+    L = brute.triangles(edges)
+    assert all(len(L[p]) == H[p] for p in range(1, 21))
+    allt = [t for p in range(1, 21) for t in L[p]]
+    assert len(set(allt)) == len(allt) == H[0]
