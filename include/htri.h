@@ -173,6 +173,17 @@ htri_status htri_get_wedges(const htri_graph *g, int32_t *src, int32_t *dst, int
 htri_status htri_count_patterns(htri_graph *g, uint32_t per_edge_pattern_mask, int64_t counts[21],
                                 int64_t *per_edge, int32_t *per_wedge, uint32_t out_flags);
 
+/* Fine-grained hypergraph clustering coefficient (Def. 5.1):
+ * 3 * sum_p epsilon[p] * counts[p] / connected_triples, with epsilon[p] in
+ * [0, 1] for p = 1..20 (epsilon[0] unused; NULL = all 1, the classical
+ * coefficient) and connected_triples = W from htri_build_wedges (summary[3],
+ * the pairs of hyperedges meeting a common one: the denominator read as
+ * the connected triples, which keeps the value in [0, 1]).  0 when W = 0.
+ * Host arithmetic only.  Errors: HTRI_E_INVALID (NULL, negative, epsilon
+ * outside [0, 1]). */
+htri_status htri_clustering_coefficient(const int64_t counts[21], int64_t connected_triples,
+                                        const double epsilon[21], double *cc);
+
 /* List the hyper-triangles of one pattern (the enumeration half of the
  * problem statement, Section 2): pattern 1..20; out receives up to capacity
  * triples of normalised hyperedge ids, each sorted ascending, in no fixed

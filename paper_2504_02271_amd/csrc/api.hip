@@ -158,6 +158,19 @@ htri_status htri_clear_wedges(htri_graph *h) {
     });
 }
 
+htri_status htri_clustering_coefficient(const int64_t counts[21], int64_t connected_triples,
+                                        const double epsilon[21], double *cc) {
+    if (!counts || !cc || connected_triples < 0) return HTRI_E_INVALID;
+    double num = 0.0;
+    for (int p = 1; p <= 20; p++) {
+        const double e = epsilon ? epsilon[p] : 1.0;
+        if (!(e >= 0.0 && e <= 1.0) || counts[p] < 0) return HTRI_E_INVALID;
+        num += e * (double)counts[p];
+    }
+    *cc = connected_triples > 0 ? 3.0 * num / (double)connected_triples : 0.0;
+    return HTRI_OK;
+}
+
 htri_status htri_enumerate(htri_graph *h, int32_t pattern, int64_t capacity, int32_t *out, int64_t *found,
                            uint32_t out_flags) {
     if (!h || !found || pattern < 1 || pattern > 20 || capacity < 0 || (capacity > 0 && !out)) return HTRI_E_INVALID;

@@ -97,6 +97,7 @@ def load_library() -> ctypes.CDLL:
         "htri_clear_wedges": ([_P], ctypes.c_int),
         "htri_closure_stats": ([_P, _P], ctypes.c_int),
         "htri_enumerate": ([_P, _i32, _i64, _P, _P, _u32], ctypes.c_int),
+        "htri_clustering_coefficient": ([_P, _i64, _P, _P], ctypes.c_int),
         "htri_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "htri_last_error": ([_P], ctypes.c_char_p),
         "htri_graph_free": ([_P], None),
@@ -329,6 +330,20 @@ class Graph:
         ms = np.zeros(6, np.float64)
         _check(self._lib.htri_last_timings(self._h, _ptr(ms)), "htri_last_timings", self._h)
         return ms
+
+
+def clustering_coefficient(counts, connected_triples: int, epsilon=None) -> float:
+    """Def. 5.1 from per-pattern counts (int64[21]) and W (summary[3]);
+    epsilon: None (all 1) or 21 weights in [0, 1] (index 0 unused)."""
+    lib = load_library()
+    c = np.ascontiguousarray(counts, dtype=np.int64)
+    e = None if epsilon is None else np.ascontiguousarray(epsilon, dtype=np.float64)
+    if c.shape != (21,) or (e is not None and e.shape != (21,)):
+        raise ValueError("counts and epsilon hold 21 entries")
+    out = ctypes.c_double(0.0)
+    _check(lib.htri_clustering_coefficient(_ptr(c), int(connected_triples), _ptr(e), ctypes.byref(out)),
+           "htri_clustering_coefficient")
+    return float(out.value)
 
 
 def graph_load(offsets, members, num_vertices: int, flags: int = HTRI_DEDUPE_EDGES,

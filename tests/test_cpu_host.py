@@ -2,6 +2,7 @@
 point, the host-side references (Philox, estimators, network gradient) are
 pinned, and the input generators are deterministic."""
 import ctypes
+import math
 import os
 import re
 
@@ -217,3 +218,31 @@ def test_pool_policy():
     from paper_2504_02271_amd import learn
     assert learn.pool_factor_for(1000, 10_000_000) == learn.POOL_FACTOR
     assert learn.pool_factor_for(100_000, 10_000_000) == 0.0
+
+
+def test_clustering_coefficient_closed_forms():
+    """Def. 5.1 through the library (host arithmetic, no GPU): a 2-uniform
+    hypergraph is a simple graph, where the classical coefficient is
+    3 * triangles / connected triples; a triangle of pairs gives 1; weights
+    select patterns; invalid weights are rejected."""
+    from oracle import brute
+    from paper_2504_02271_amd import htri
+    tri = [[0, 1], [1, 2], [0, 2]]
+    H, _ = brute.count(tri)
+    W = sum(math.comb(2, 2) for _ in range(3))           # each hyperedge meets the other two
+    assert htri.clustering_coefficient(H, W) == pytest.approx(1.0)
+    rng = np.random.default_rng(3)
+    pairs = {tuple(sorted(rng.choice(12, size=2, replace=False).tolist())) for _ in range(30)}
+    edges = [list(p) for p in sorted(pairs)]
+    H, _ = brute.count(edges)
+    deg = [sum(1 for f in edges if f != e and set(e) & set(f)) for e in edges]
+    W = sum(d * (d - 1) // 2 for d in deg)
+    assert htri.clustering_coefficient(H, W) == pytest.approx(3 * H[0] / W)
+    eps = np.zeros(21)
+    eps[17] = 0.5
+    assert htri.clustering_coefficient(H, W, eps) == pytest.approx(1.5 * H[17] / W)
+    assert htri.clustering_coefficient(H, 0) == 0.0
+    bad = np.zeros(21)
+    bad[3] = 1.5
+    with pytest.raises(htri.HtriError):
+        htri.clustering_coefficient(H, W, bad)
