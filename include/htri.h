@@ -219,12 +219,18 @@ htri_status htri_closure_stats(const htri_graph *g, int64_t out[12]);
 
 typedef struct htri_model htri_model;
 
+/* Sampling flag: close every inclusion hyperwedge exactly (a small stratum)
+ * and sample only the intersection-type ones, whose sampled closures carry
+ * the estimate of the rest (separate sampling of the two hyperwedge types,
+ * as in Appro-adv, Algorithm 7, with the inclusion stratum exhausted). */
+#define HTRI_SAMPLE_EXACT_INCLUSION 1
+
 typedef struct {
     double budget_fraction;   /* samples = budget_fraction * |wedges| ...      */
     int64_t num_samples;      /* ... unless num_samples > 0                    */
     uint64_t seed;            /* Philox-4x32-10 key                            */
     int32_t proposal;         /* 0 = uniform, 1 = learned                      */
-    int32_t reserved;
+    int32_t flags;            /* HTRI_SAMPLE_EXACT_INCLUSION or 0              */
     const htri_model *model;  /* required for proposal 1                       */
     double defensive_mix;     /* lambda: q = (1-lambda) q_model + lambda/|pool| */
     double pool_factor;       /* learned: candidate pool = pool_factor*samples  */

@@ -1442,6 +1442,25 @@ __global__ void k_incl_pairs(const int64_t *fptr, const uint32_t *fadj, const in
     }
 }
 
+// forward-adjacency positions of the inclusion hyperwedges; one wave per owner
+__global__ void k_incl_index(const int64_t *fptr, const uint32_t *fadj, const int32_t *esize, int64_t m, int wbits,
+                             unsigned long long *n, int64_t cap, int64_t *idx) {
+    const uint32_t wmask = (1u << wbits) - 1;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; r < m; r += nwaves) {
+        const int32_t sr = esize[r];
+        for (int64_t e = fptr[r] + lane; e < fptr[r + 1]; e += kWave) {
+            const uint32_t ent = fadj[e];
+            const int32_t sj = esize[ent >> wbits];
+            if ((int32_t)(ent & wmask) == (sr < sj ? sr : sj)) {
+                const unsigned long long at = atomicAdd(n, 1ull);
+                if ((int64_t)at < cap) idx[at] = e;
+            }
+        }
+    }
+}
+
 // |e_a & e_b| of two sorted member lists, and their smallest common vertex (or -1)
 __device__ __forceinline__ int common_members(const int64_t *eptr, const int32_t *emem, int32_t a, int32_t b,
                                               int32_t &first) {
@@ -1527,6 +1546,24 @@ __global__ __launch_bounds__(kBlock) void k_incl_count(const int2 *pairs, const 
 }
 
 }  // namespace
+
+int64_t list_inclusion_wedges(Graph &g, DBuf<int64_t> &out) {
+    hipStream_t s = g.stream;
+    const int64_t nc = g.summary[2];
+    out.alloc(g.al, nc);
+    DBuf<unsigned long long> n(g.al, 1);
+    fill_u64((uint64_t *)n.p, 1, 0, s);
+    if (g.m > 0 && nc > 0) {
+        hipLaunchKernelGGL(k_incl_index, dim3(grid_for(g.m * kWave, 256, 8192)), dim3(256), 0, s, g.fptr.p, g.fadj.p,
+                           g.esize.p, g.m, g.wbits, n.p, nc, out.p);
+        HTRI_LAUNCH_CHECK();
+    }
+    unsigned long long found = 0;
+    HTRI_HIP(hipMemcpyAsync(&found, n.p, sizeof(found), hipMemcpyDeviceToHost, s));
+    HTRI_HIP(hipStreamSynchronize(s));
+    if ((int64_t)found != nc) fail(HTRI_E_DEVICE, "inclusion hyperwedge count differs from step 1");
+    return nc;
+}
 
 void count_inclusion_classes(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev, int target,
                              int64_t capacity, int32_t *dev_out, unsigned long long *dev_found) {

@@ -3,6 +3,7 @@
 // proposal, optionally over a uniform candidate pool.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -80,8 +81,23 @@ htri_status htri_estimate(htri_graph *h, const htri_sample_params *p, double est
         HTRI_HIP(hipEventRecord(e0, s));
         long long c[21];
         double y[21], y2[21];
+        // the inclusion stratum closed exactly: its closures are summed and
+        // the sampled part counts only intersection-type hyperwedges
+        const bool strat = (p->flags & HTRI_SAMPLE_EXACT_INCLUSION) != 0;
+        double exact[21] = {0};
+        if (strat && g.summary[2] > 0) {
+            DBuf<int64_t> idx;
+            const int64_t nc = list_inclusion_wedges(g, idx);
+            DBuf<int64_t> cl(g.al, nc * 21);
+            close_wedge_list_counts(g, idx.p, nc, cl.p);
+            std::vector<int64_t> hc((size_t)nc * 21);
+            HTRI_HIP(hipMemcpyAsync(hc.data(), cl.p, sizeof(int64_t) * nc * 21, hipMemcpyDeviceToHost, s));
+            HTRI_HIP(hipStreamSynchronize(s));
+            for (int64_t w = 0; w < nc; w++)
+                for (int q = 0; q < 21; q++) exact[q] += (double)hc[(size_t)w * 21 + q];
+        }
         if (p->proposal == 0) {
-            sample_sums(g, 1, n, p->seed, nullptr, nullptr, 0, (double)nw, c, y, y2);
+            sample_sums(g, 1, n, p->seed, nullptr, nullptr, 0, (double)nw, c, y, y2, strat);
             HTRI_HIP(hipEventRecord(e1, s));
             for (int q = 0; q < 21; q++) e[q] = (double)c[q] * (double)nw / (double)n;
         } else {
@@ -98,7 +114,7 @@ htri_status htri_estimate(htri_graph *h, const htri_sample_params *p, double est
             scan_inclusive_f64(g.al, score.p, cdf.p, P, s);
             hipLaunchKernelGGL(k_mix_cdf, dim3(grid_for(P, 256, 8192)), dim3(256), 0, s, cdf.p, P, p->defensive_mix);
             HTRI_LAUNCH_CHECK();
-            sample_sums(g, 2, n, p->seed, pool.p, cdf.p, P, (double)nw / (double)P, c, y, y2);
+            sample_sums(g, 2, n, p->seed, pool.p, cdf.p, P, (double)nw / (double)P, c, y, y2, strat);
             HTRI_HIP(hipEventRecord(e1, s));
             for (int q = 0; q < 21; q++) e[q] = y[q] / (double)n;
         }
@@ -110,6 +126,7 @@ htri_status htri_estimate(htri_graph *h, const htri_sample_params *p, double est
         for (int q = 0; q < 21; q++) {
             const double var = (y2[q] - (double)n * e[q] * e[q]) / ((double)n * (double)std::max<int64_t>(n - 1, 1));
             se[q] = std::sqrt(std::max(var, 0.0));
+            e[q] += exact[q];
         }
         std::memcpy(est, e, sizeof(e));
         if (stderr_) std::memcpy(stderr_, se, sizeof(se));

@@ -255,7 +255,10 @@ void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21],
 // sums over uniform (mode 1) or pool (mode 2) draws
 void close_wedge_list_counts(Graph &g, const int64_t *dev_idx, int64_t n, int64_t *dev_out);
 void sample_sums(Graph &g, int mode, int64_t n, uint64_t seed, const int64_t *pool, const double *cdf,
-                 int64_t pool_n, double scale, long long c[21], double y[21], double y2[21]);
+                 int64_t pool_n, double scale, long long c[21], double y[21], double y2[21],
+                 bool skip_inclusion = false);
+// positions (forward-adjacency indices) of every inclusion hyperwedge
+int64_t list_inclusion_wedges(Graph &g, DBuf<int64_t> &out);
 void draw_pool(Graph &g, uint64_t seed, int64_t pool_n, int64_t *dev_pool);
 void scan_inclusive_f64(Allocator &a, const double *in, double *out, int64_t n, hipStream_t s);
 

@@ -70,6 +70,7 @@ struct SampleArgs {
     const double *cdf;          // inclusive CDF over the pool
     int64_t pool_n;
     double scale;               // multiplies every closure (mode 1: |wedges|; mode 2: |wedges|/pool)
+    int skip_inclusion;         // drawn inclusion hyperwedges close nothing (their stratum is exact)
     // accumulation: per wave [21] x (int64 sum c, double sum y, double sum y^2)
     long long *acc_c;
     double *acc_y;
@@ -102,6 +103,7 @@ __device__ long long wave_close_f(const SampleArgs &A, const uint8_t *lut, int64
     const uint32_t j = jent >> A.wbits;
     const int wrj = (int)(jent & wmask);
     const int si = A.esize[r], sj = A.esize[j];
+    if (A.skip_inclusion && wrj == (si < sj ? si : sj)) return 0;
     const int W = mask_words(si);
     const int64_t mbase = A.mptr[r];
     uint32_t mj[kMaskWordsMax];
@@ -320,7 +322,7 @@ void enumerate_all_wedges(Graph &g, int target, int64_t capacity, int32_t *dev_o
 // Weighted closure sums over n draws.  mode 1: uniform (scale = |wedges|);
 // mode 2: from a pool by its CDF (scale = |wedges| / pool size).
 void sample_sums(Graph &g, int mode, int64_t n, uint64_t seed, const int64_t *pool, const double *cdf,
-                 int64_t pool_n, double scale, long long c[21], double y[21], double y2[21]) {
+                 int64_t pool_n, double scale, long long c[21], double y[21], double y2[21], bool skip_inclusion) {
     hipStream_t s = g.stream;
     Allocator &A = g.al;
     DBuf<uint8_t> lut(A, 128);
@@ -336,6 +338,7 @@ void sample_sums(Graph &g, int mode, int64_t n, uint64_t seed, const int64_t *po
     a.cdf = cdf;
     a.pool_n = pool_n;
     a.scale = scale;
+    a.skip_inclusion = skip_inclusion ? 1 : 0;
     a.acc_c = ac.p;
     a.acc_y = ay.p;
     a.acc_y2 = ay2.p;

@@ -23,6 +23,7 @@ HTRI_ORDER_INPUT = 8
 HTRI_COUNT_NO_WINDOW = 16
 HTRI_COUNT_WINDOW_ALWAYS = 32
 HTRI_COUNT_INCLUSION_CLASSES = 64
+HTRI_SAMPLE_EXACT_INCLUSION = 1
 _WINDOW_FLAGS = {"auto": 0, "off": HTRI_COUNT_NO_WINDOW, "always": HTRI_COUNT_WINDOW_ALWAYS,
                  "inclusion_classes": HTRI_COUNT_INCLUSION_CLASSES}
 HTRI_MODEL_NUM_PARAMS = 5313
@@ -55,7 +56,7 @@ class Allocator(ctypes.Structure):
 
 class SampleParams(ctypes.Structure):
     _fields_ = [("budget_fraction", ctypes.c_double), ("num_samples", ctypes.c_int64),
-                ("seed", ctypes.c_uint64), ("proposal", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("proposal", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("model", ctypes.c_void_p), ("defensive_mix", ctypes.c_double),
                 ("pool_factor", ctypes.c_double)]
 
@@ -297,9 +298,12 @@ class Graph:
         return out
 
     def estimate(self, budget: float = 0.01, num_samples: int = 0, seed: int = 0, proposal: int = 0,
-                 model: "Optional[Model]" = None, defensive_mix: float = 0.1, pool_factor: float = 0.0):
-        """Hyperwedge-sampling estimate: (est float64[21], stderr float64[21], device ms)."""
-        p = SampleParams(float(budget), int(num_samples), int(seed) & 0xFFFFFFFFFFFFFFFF, int(proposal), 0,
+                 model: "Optional[Model]" = None, defensive_mix: float = 0.1, pool_factor: float = 0.0,
+                 exact_inclusion: bool = False):
+        """Hyperwedge-sampling estimate: (est float64[21], stderr float64[21], device ms).
+        exact_inclusion: close every inclusion hyperwedge exactly, sample the rest."""
+        p = SampleParams(float(budget), int(num_samples), int(seed) & 0xFFFFFFFFFFFFFFFF, int(proposal),
+                         HTRI_SAMPLE_EXACT_INCLUSION if exact_inclusion else 0,
                          model._h if model is not None else None, float(defensive_mix), float(pool_factor))
         est = np.zeros(21, np.float64)
         se = np.zeros(21, np.float64)

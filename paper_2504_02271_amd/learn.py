@@ -104,9 +104,9 @@ def relative_error(est: np.ndarray, exact: np.ndarray) -> float:
     return float(np.mean(np.abs(H[nz] - est[1:][nz]) / H[nz]))
 
 
-def _run(G, proposal, n, seed, model, mix, pool_factor):
+def _run(G, proposal, n, seed, model, mix, pool_factor, exact_inclusion=False):
     return G.estimate(num_samples=n, seed=seed, proposal=proposal, model=model, defensive_mix=mix,
-                      pool_factor=pool_factor)
+                      pool_factor=pool_factor, exact_inclusion=exact_inclusion)
 
 
 POOL_FACTOR = 16.0
@@ -125,36 +125,39 @@ def pool_factor_for(n: int, nw: int, pool_factor: float = POOL_FACTOR,
 
 def equal_time_study(G, exact: np.ndarray, model, budgets: Sequence[float] = (0.001, 0.01, 0.05),
                      seeds: int = 32, mix: float = 0.1, pool_factor="auto",
-                     log=print) -> List[Dict]:
+                     log=print, exact_inclusion: bool = False) -> List[Dict]:
     """Learned vs uniform hyperwedge sampling at equal GPU time.  For each
     budget b: the learned sampler draws b*|wedges| samples (from a uniform pool
     of pool_factor times as many candidates, or from all wedges with pool
     factor 0; "auto" picks with pool_factor_for); its device time sets the
     time budget; the uniform sampler gets as many samples as fit in that time
-    (calibrated to within 5%).  Errors over `seeds` independent runs."""
+    (calibrated to within 5%).  Errors over `seeds` independent runs.
+    exact_inclusion: both samplers close the inclusion stratum exactly and
+    sample the intersection-type hyperwedges."""
+    xi = exact_inclusion
     nw = G.num_wedges
     out = []
     for b in budgets:
         nL = max(1, int(round(b * nw)))
         pf = pool_factor_for(nL, nw) if pool_factor == "auto" else float(pool_factor)
-        _run(G, 1, nL, 10_000, model, mix, pf)                 # warm-up
+        _run(G, 1, nL, 10_000, model, mix, pf, xi)                 # warm-up
         rl, tl, el = [], [], []
         for s in range(seeds):
-            est, se, ms = _run(G, 1, nL, s, model, mix, pf)
+            est, se, ms = _run(G, 1, nL, s, model, mix, pf, xi)
             rl.append(relative_error(est, exact))
             tl.append(ms)
             el.append(est)
         t_target = float(np.median(tl))
         nU = nL
         for _ in range(6):                                              # calibrate the uniform count
-            ts = [_run(G, 0, nU, 20_000 + r, None, 0, 0)[2] for r in range(3)]
+            ts = [_run(G, 0, nU, 20_000 + r, None, 0, 0, xi)[2] for r in range(3)]
             t = float(np.median(ts))
             if abs(t - t_target) <= 0.05 * t_target:
                 break
             nU = max(1, int(nU * t_target / max(t, 1e-6)))
         ru, tu, eu = [], [], []
         for s in range(seeds):
-            est, se, ms = _run(G, 0, nU, s, None, 0, 0)
+            est, se, ms = _run(G, 0, nU, s, None, 0, 0, xi)
             ru.append(relative_error(est, exact))
             tu.append(ms)
             eu.append(est)
@@ -164,7 +167,8 @@ def equal_time_study(G, exact: np.ndarray, model, budgets: Sequence[float] = (0.
             pl = np.where(H > 0, np.abs(el - H).mean(axis=0) / H, np.nan)[1:]
             pu = np.where(H > 0, np.abs(eu - H).mean(axis=0) / H, np.nan)[1:]
         row = {
-            "budget": b, "learned_samples": nL, "uniform_samples": nU, "pool_factor": pf,
+            "budget": b, "exact_inclusion": bool(xi), "learned_samples": nL, "uniform_samples": nU,
+            "pool_factor": pf,
             "learned_ms": t_target, "uniform_ms": float(np.median(tu)),
             "learned_rel_err": float(np.mean(rl)), "uniform_rel_err": float(np.mean(ru)),
             "learned_total_rel_err": float(np.mean(np.abs(el[:, 0] - H[0]) / H[0])),
