@@ -33,6 +33,8 @@ WORKLOADS = {
     "coauth": "co-authorship-shaped: |V|=1e5, |E|=5e5 drawn, sizes truncated power law on [2,25] "
               "(exponent 2.5), Zipf(1.1) head with d_max=2e3 plus background, seed 2",
     "tiny": "uniform: |V|=1e3, |E|=2e3, sizes uniform on [2,5], seed 0",
+    "tags_stress": "tags/threads-shaped stress: as tags with the Zipf head d_max=1e5 (one vertex in 1e5 "
+                   "hyperedges), seed 3",
 }
 
 

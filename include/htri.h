@@ -146,6 +146,12 @@ htri_status htri_clear_wedges(htri_graph *g);
  * NULL.  This is the order of per_wedge in htri_count_patterns. */
 htri_status htri_get_wedges(const htri_graph *g, int32_t *src, int32_t *dst, int32_t *omega);
 
+/* The same for listed hyperwedges only (indices into the htri_get_wedges
+ * order, host arrays of n entries; omega may be NULL): for hypergraphs whose
+ * whole wedge list is too large to copy. */
+htri_status htri_get_wedge_list(const htri_graph *g, const int64_t *wedge_idx, int64_t n, int32_t *src,
+                                int32_t *dst, int32_t *omega);
+
 /* Step 2 (Algorithms 3 and 5 as Exact-adv): exact count of every pattern.
  *   per_edge_pattern_mask  bit p (1..20) set: triangles of pattern p count
  *                          in per_edge.  0 is taken as "all patterns".
@@ -163,11 +169,11 @@ htri_status htri_get_wedges(const htri_graph *g, int32_t *src, int32_t *dst, int
  *               (patterns 1-8; Count-CCC, Count-TCC and Count-TTC of
  *               Section 3.1 search only around those hyperwedges): counts[p]
  *               for p > 8 are 0, per_edge counts the masked triangles of
- *               patterns 1-8.  By default
- *               the owners of the top ranks (up to 16384 of them) are closed
- *               by bitmap intersection when the hyperwedges among them are
- *               dense (at least 1/16 of all pairs); the counts do not
- *               depend on the choice.
+ *               patterns 1-8.  By default the owners of the top ranks (the
+ *               whole graph or a power of two of them, up to 131072) are
+ *               closed by bitmap intersection when the hyperwedges among
+ *               them fill at least 1/8 of all pairs (the largest such set);
+ *               the counts do not depend on the choice.
  * Errors: HTRI_E_STATE (no wedges yet), HTRI_E_INVALID (unknown flag),
  * HTRI_E_OOM, HTRI_E_DEVICE. */
 htri_status htri_count_patterns(htri_graph *g, uint32_t per_edge_pattern_mask, int64_t counts[21],

@@ -2,6 +2,7 @@
 #include <mutex>
 
 #include <algorithm>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -236,6 +237,58 @@ htri_status htri_get_wedges(const htri_graph *hc, int32_t *src, int32_t *dst, in
                 dst[e] = nor[fadj[e] >> g.wbits];
                 if (omega) omega[e] = (int32_t)(fadj[e] & wmask);
             }
+    });
+}
+
+namespace {
+// endpoints and omega of listed hyperwedges (owner by binary search in fptr)
+__global__ void k_wedge_list(const int64_t *fptr, const uint32_t *fadj, const int32_t *norm_of_rank, int64_t m,
+                             int wbits, const int64_t *idx, int64_t n, int32_t *out) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = idx[t];
+        int64_t lo = 0, hi = m;                  // largest r with fptr[r] <= e
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (fptr[mid] <= e) lo = mid; else hi = mid;
+        }
+        const uint32_t ent = fadj[e];
+        out[t * 3 + 0] = norm_of_rank[lo];
+        out[t * 3 + 1] = norm_of_rank[ent >> wbits];
+        out[t * 3 + 2] = (int32_t)(ent & ((1u << wbits) - 1));
+    }
+}
+}  // namespace
+
+htri_status htri_get_wedge_list(const htri_graph *hc, const int64_t *wedge_idx, int64_t n, int32_t *src,
+                                int32_t *dst, int32_t *omega) {
+    htri_graph *h = const_cast<htri_graph *>(hc);
+    if (!h || n < 0 || (n > 0 && (!wedge_idx || !src || !dst))) return HTRI_E_INVALID;
+    if (!h->g.have_wedges) {
+        h->g.err = "htri_build_wedges has not run";
+        return HTRI_E_STATE;
+    }
+    for (int64_t t = 0; t < n; t++)
+        if (wedge_idx[t] < 0 || wedge_idx[t] >= h->g.nw) {
+            h->g.err = "wedge index out of range";
+            return HTRI_E_INVALID;
+        }
+    return run(&h->g, [&] {
+        htri::Graph &g = h->g;
+        if (n == 0) return;
+        htri::DBuf<int64_t> idx(g.al, n);
+        htri::DBuf<int32_t> out(g.al, n * 3);
+        HTRI_HIP(hipMemcpyAsync(idx.p, wedge_idx, sizeof(int64_t) * n, hipMemcpyHostToDevice, g.stream));
+        hipLaunchKernelGGL(k_wedge_list, dim3(htri::grid_for(n, 256)), dim3(256), 0, g.stream, g.fptr.p, g.fadj.p,
+                           g.norm_of_rank.p, g.m, g.wbits, idx.p, n, out.p);
+        HTRI_LAUNCH_CHECK();
+        std::vector<int32_t> h3((size_t)n * 3);
+        HTRI_HIP(hipMemcpyAsync(h3.data(), out.p, sizeof(int32_t) * n * 3, hipMemcpyDeviceToHost, g.stream));
+        HTRI_HIP(hipStreamSynchronize(g.stream));
+        for (int64_t t = 0; t < n; t++) {
+            src[t] = h3[(size_t)t * 3];
+            dst[t] = h3[(size_t)t * 3 + 1];
+            if (omega) omega[t] = h3[(size_t)t * 3 + 2];
+        }
     });
 }
 

@@ -1056,15 +1056,46 @@ namespace {
 // private vertex), i.e. |K_v & BF1_j|.  The owner's kWinClasses largest
 // classes are counted this way; the other hits are enumerated bit by bit and
 // classified by their regions like probed hits.
-constexpr int kWinRowsMax = 16384;
+constexpr int kWinRowsMax = 131072;
 constexpr int kWinWordsMax = kWinRowsMax / 32;
-constexpr int kWinClasses = 8;
+constexpr int kWinClasses = 8;              // bulk-counted classes at most (fewer for wide windows)
+constexpr int kWinLdsBudget = 60 * 1024;    // bytes of row bitmaps per block of k_close_window
 
+// exclusive prefix of popcounts of x[0..n) into out (n up to kWinWordsMax),
+// whole block, contiguous chunks per thread
+__device__ __forceinline__ void block_popcount_prefix(const uint32_t *x, int n, int32_t *out, int32_t *wsum) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int per = (n + nt - 1) / nt;
+    const int a = tid * per, b = min(n, a + per);
+    int own = 0;
+    for (int w = a; w < b; w++) own += __popc(x[w]);
+    int incl = own;
+    const int lane = tid & (kWave - 1), wv = tid / kWave;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int u = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += u;
+    }
+    if (lane == kWave - 1) wsum[wv] = incl;
+    __syncthreads();
+    int run = incl - own;
+    for (int q = 0; q < wv; q++) run += wsum[q];
+    for (int w = a; w < b; w++) {
+        out[w] = run;
+        run += __popc(x[w]);
+    }
+    __syncthreads();
+}
+
+// one block per window row; dynamic shared memory: two rows of nwords words
+// and their prefix
 __global__ __launch_bounds__(256) void k_window_rows(const int64_t *fptr, const uint32_t *fadj, int wbits, int64_t w0,
                                                      int nwords, uint32_t *bf, uint32_t *bf1, uint32_t *bi1,
-                                                     uint16_t *pf) {
-    __shared__ uint32_t rf[kWinWordsMax], r1[kWinWordsMax];
-    __shared__ uint32_t wsum[256 / kWave];
+                                                     uint32_t *pf) {
+    extern __shared__ uint32_t dyn[];
+    uint32_t *rf = dyn, *r1 = dyn + nwords;
+    int32_t *pre = (int32_t *)(dyn + 2 * nwords);
+    __shared__ int32_t wsum[256 / kWave];
     const int tid = threadIdx.x;
     const int row = blockIdx.x;
     const uint32_t wmask = (1u << wbits) - 1;
@@ -1081,31 +1112,12 @@ __global__ __launch_bounds__(256) void k_window_rows(const int64_t *fptr, const 
         }
     }
     __syncthreads();
-    // rows out; exclusive popcount prefix, two words per thread
-    const int w_a = 2 * tid, w_b = 2 * tid + 1;
-    const int ca = w_a < nwords ? __popc(rf[w_a]) : 0, cb = w_b < nwords ? __popc(rf[w_b]) : 0;
-    int incl = ca + cb;
-    const int lane = tid & (kWave - 1), wv = tid / kWave;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const int u = __shfl_up(incl, o, kWave);
-        if (lane >= o) incl += u;
-    }
-    if (lane == kWave - 1) wsum[wv] = incl;
-    __syncthreads();
-    int before = 0;
-    for (int q = 0; q < wv; q++) before += wsum[q];
-    const int ex = before + incl - ca - cb;
+    block_popcount_prefix(rf, nwords, pre, wsum);
     const int64_t ro = (int64_t)row * nwords;
-    if (w_a < nwords) {
-        bf[ro + w_a] = rf[w_a];
-        bf1[ro + w_a] = r1[w_a];
-        pf[ro + w_a] = (uint16_t)ex;
-    }
-    if (w_b < nwords) {
-        bf[ro + w_b] = rf[w_b];
-        bf1[ro + w_b] = r1[w_b];
-        pf[ro + w_b] = (uint16_t)(ex + ca);
+    for (int w = tid; w < nwords; w += blockDim.x) {
+        bf[ro + w] = rf[w];
+        bf1[ro + w] = r1[w];
+        pf[ro + w] = (uint32_t)pre[w];
     }
 }
 
@@ -1114,7 +1126,8 @@ struct WinArgs {
     int64_t w0;
     int nrows, nwords;
     const uint32_t *bf, *bf1, *bi1;
-    const uint16_t *pf;
+    const uint32_t *pf;
+    int max_classes;                // class bitmaps that fit the block's shared memory
     const uint8_t *lut;
     uint32_t emask;
     unsigned int *queue;
@@ -1123,10 +1136,14 @@ struct WinArgs {
     uint32_t *cwj, *cwjm, *cwkm;
 };
 
+// dynamic shared memory: BR, PR and max_classes class rows of nwords words
 template <bool PER_EDGE, bool PER_WEDGE>
 __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
-    __shared__ uint32_t BR[kWinWordsMax], BK[kWinClasses][kWinWordsMax];
-    __shared__ int32_t PR[kWinWordsMax];
+    extern __shared__ uint32_t dyn[];
+    uint32_t *BR = dyn;
+    int32_t *PR = (int32_t *)(dyn + A.nwords);
+    uint32_t *BKbase = dyn + 2 * A.nwords;
+    auto BK = [&](int c) { return BKbase + (int64_t)c * A.nwords; };
     __shared__ uint32_t cls[32 * kMaskWordsMax];
     __shared__ int32_t cslot[32 * kMaskWordsMax];  // class slot of member position v, or -1
     __shared__ int32_t wsum[kBlock / kWave];
@@ -1184,7 +1201,7 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
             const int npos = 32 * W;
             for (int v = 0; v < 32 * kMaskWordsMax; v++) cslot[v] = -1;
             if (classes) {
-                for (; nc < kWinClasses; nc++) {
+                for (; nc < A.max_classes; nc++) {
                     int best = -1;
                     uint32_t bc = 1;
                     for (int v = 0; v < npos; v++)
@@ -1195,26 +1212,10 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
             }
             sh_nc = nc;
         }
-        // exclusive popcount prefix of BR (positions in N+(r)), two words per thread
-        {
-            const int w_a = 2 * tid, w_b = 2 * tid + 1;
-            const int ca = w_a < nwords ? __popc(BR[w_a]) : 0, cb = w_b < nwords ? __popc(BR[w_b]) : 0;
-            int incl = ca + cb;
-#pragma unroll
-            for (int o = 1; o < kWave; o <<= 1) {
-                const int u = __shfl_up(incl, o, kWave);
-                if (lane >= o) incl += u;
-            }
-            if (lane == kWave - 1) wsum[wave] = incl;
-            __syncthreads();
-            int before = 0;
-            for (int q = 0; q < wave; q++) before += wsum[q];
-            const int ex = before + incl - ca - cb;
-            if (w_a < nwords) PR[w_a] = ex;
-            if (w_b < nwords) PR[w_b] = ex + ca;
-        }
+        // exclusive popcount prefix of BR (positions in N+(r)); ends with a barrier
+        block_popcount_prefix(BR, nwords, PR, wsum);
         const int nc = sh_nc;
-        for (int t = tid; t < nc * nwords; t += kBlock) BK[t / nwords][t % nwords] = 0u;
+        for (int t = tid; t < nc * nwords; t += kBlock) BKbase[t] = 0u;
         __syncthreads();
         // class slot of an entry of N+(r), or -1
         auto class_of = [&](uint32_t ent, int64_t q) -> int {
@@ -1228,7 +1229,7 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
                 const int c = class_of(ent, q);
                 if (c >= 0) {
                     const int kr = (int)((int64_t)(ent >> wbits) - A.w0);
-                    atomicOr(&BK[c][kr >> 5], 1u << (kr & 31));
+                    atomicOr(&BK(c)[kr >> 5], 1u << (kr & 31));
                 }
             }
         }
@@ -1242,7 +1243,7 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
                 uint32_t kf = 0;
                 if (c >= 0) {
                     const uint32_t *bik = A.bi1 + (int64_t)kr * nwords;
-                    for (int w = (row >> 5) + lane; w <= (kr >> 5); w += kWave) kf += __popc(BK[c][w] & gld(bik + w));
+                    for (int w = (row >> 5) + lane; w <= (kr >> 5); w += kWave) kf += __popc(BK(c)[w] & gld(bik + w));
                     words_read += (unsigned long long)((kr >> 5) - (row >> 5) + 1);
 #pragma unroll
                     for (int o = kWave / 2; o > 0; o >>= 1) kf += __shfl_xor(kf, o, kWave);
@@ -1266,13 +1267,13 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
             const int64_t jbase = gld(G.fptr + j);
             const uint32_t *bfj = A.bf + (int64_t)jr * nwords;
             const uint32_t *bf1j = A.bf1 + (int64_t)jr * nwords;
-            const uint16_t *pfj = A.pf + (int64_t)jr * nwords;
+            const uint32_t *pfj = A.pf + (int64_t)jr * nwords;
             uint32_t all = 0, fast = 0, menum = 0;
             for (int w = (jr >> 5) + lane; w < nwords; w += kWave) {
                 const uint32_t bw = gld(bfj + w);
                 const uint32_t a = BR[w] & bw;
                 all += __popc(a);
-                const uint32_t fs = dom ? (BK[cj][w] & gld(bf1j + w)) : 0u;
+                const uint32_t fs = dom ? (BK(cj)[w] & gld(bf1j + w)) : 0u;
                 fast += __popc(fs);
                 uint32_t non = a & ~fs;
                 while (non) {
@@ -1340,20 +1341,23 @@ WindowPlan choose_window(Graph &g, uint32_t flags) {
         return v;
     };
     const int64_t e_end = fptr_at(g.m);
-    for (int64_t cand = kWinRowsMax; cand >= 1024; cand /= 2) {
-        const int64_t n = std::min<int64_t>(g.m, cand);
+    // candidates: the whole graph (or the largest window), then every power of
+    // two below it down to 1024 rows
+    std::vector<int64_t> cands{std::min<int64_t>(g.m, kWinRowsMax)};
+    for (int64_t c = kWinRowsMax; c >= 1024; c /= 2)
+        if (c < cands[0]) cands.push_back(c);
+    for (const int64_t n : cands) {
         const int64_t w0 = g.m - n;
         const int64_t inside = e_end - fptr_at(w0);
         if (inside == 0) continue;
         const double density = (double)inside / (0.5 * (double)n * (double)n);
-        if ((flags & HTRI_COUNT_WINDOW_ALWAYS) || density >= 1.0 / 16.0) {
+        if ((flags & HTRI_COUNT_WINDOW_ALWAYS) || density >= 1.0 / 8.0) {
             w.w0 = w0;
             w.nrows = (int)n;
             w.nwords = (int)((n + 31) / 32);
             w.wedges = inside;
             return w;
         }
-        if (n < cand) break;      // the whole graph was the candidate
     }
     return w;
 }
@@ -1365,12 +1369,12 @@ void close_window(Graph &g, const WindowPlan &w, uint32_t emask, const uint8_t *
     Allocator &A = g.al;
     const int64_t cells = (int64_t)w.nrows * w.nwords;
     DBuf<uint32_t> bf(A, cells), bf1(A, cells), bi1(A, cells);
-    DBuf<uint16_t> pf(A, cells);
+    DBuf<uint32_t> pf(A, cells);
     DBuf<unsigned int> queue(A, 1);
     fill_u32(bi1.p, cells, 0, s);
     fill_u32(queue.p, 1, 0, s);
-    hipLaunchKernelGGL(k_window_rows, dim3(w.nrows), dim3(256), 0, s, g.fptr.p, g.fadj.p, g.wbits, w.w0, w.nwords,
-                       bf.p, bf1.p, bi1.p, pf.p);
+    hipLaunchKernelGGL(k_window_rows, dim3(w.nrows), dim3(256), (size_t)3 * w.nwords * sizeof(uint32_t), s, g.fptr.p,
+                       g.fadj.p, g.wbits, w.w0, w.nwords, bf.p, bf1.p, bi1.p, pf.p);
     HTRI_LAUNCH_CHECK();
     WinArgs a;
     a.G = graph_desc(g);
@@ -1381,6 +1385,8 @@ void close_window(Graph &g, const WindowPlan &w, uint32_t emask, const uint8_t *
     a.bf1 = bf1.p;
     a.bi1 = bi1.p;
     a.pf = pf.p;
+    a.max_classes = std::max(0, std::min(kWinClasses, kWinLdsBudget / (4 * w.nwords) - 2));
+    const size_t shmem = (size_t)(2 + a.max_classes) * w.nwords * sizeof(uint32_t);
     a.lut = lut_dev;
     a.emask = emask;
     a.queue = queue.p;
@@ -1392,16 +1398,16 @@ void close_window(Graph &g, const WindowPlan &w, uint32_t emask, const uint8_t *
     const bool pe = cwjm != nullptr, pw = cwj != nullptr;
     int nb = 0;
     hipError_t oe;
-    if (pe && pw) oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_close_window<true, true>, kBlock, 0);
-    else if (pe) oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_close_window<true, false>, kBlock, 0);
-    else if (pw) oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_close_window<false, true>, kBlock, 0);
-    else oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_close_window<false, false>, kBlock, 0);
+    if (pe && pw) oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_close_window<true, true>, kBlock, shmem);
+    else if (pe) oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_close_window<true, false>, kBlock, shmem);
+    else if (pw) oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_close_window<false, true>, kBlock, shmem);
+    else oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_close_window<false, false>, kBlock, shmem);
     if (oe != hipSuccess || nb < 1) nb = 1;
     const int grid = (int)std::min<int64_t>((int64_t)device_cu_count() * nb, w.nrows);
-    if (pe && pw) hipLaunchKernelGGL((k_close_window<true, true>), dim3(grid), dim3(kBlock), 0, s, a);
-    else if (pe) hipLaunchKernelGGL((k_close_window<true, false>), dim3(grid), dim3(kBlock), 0, s, a);
-    else if (pw) hipLaunchKernelGGL((k_close_window<false, true>), dim3(grid), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_close_window<false, false>), dim3(grid), dim3(kBlock), 0, s, a);
+    if (pe && pw) hipLaunchKernelGGL((k_close_window<true, true>), dim3(grid), dim3(kBlock), shmem, s, a);
+    else if (pe) hipLaunchKernelGGL((k_close_window<true, false>), dim3(grid), dim3(kBlock), shmem, s, a);
+    else if (pw) hipLaunchKernelGGL((k_close_window<false, true>), dim3(grid), dim3(kBlock), shmem, s, a);
+    else hipLaunchKernelGGL((k_close_window<false, false>), dim3(grid), dim3(kBlock), shmem, s, a);
     HTRI_LAUNCH_CHECK();
     // the bitmaps are freed when this returns: wait for the kernels
     HTRI_HIP(hipStreamSynchronize(s));

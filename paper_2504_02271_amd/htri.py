@@ -99,6 +99,7 @@ def load_library() -> ctypes.CDLL:
         "htri_closure_stats": ([_P, _P], ctypes.c_int),
         "htri_enumerate": ([_P, _i32, _i64, _P, _P, _u32], ctypes.c_int),
         "htri_clustering_coefficient": ([_P, _i64, _P, _P], ctypes.c_int),
+        "htri_get_wedge_list": ([_P, _P, _i64, _P, _P, _P], ctypes.c_int),
         "htri_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "htri_last_error": ([_P], ctypes.c_char_p),
         "htri_graph_free": ([_P], None),
@@ -244,6 +245,17 @@ class Graph:
         dst = np.zeros(nw, np.int32)
         om = np.zeros(nw, np.int32)
         _check(self._lib.htri_get_wedges(self._h, _ptr(src), _ptr(dst), _ptr(om)), "htri_get_wedges", self._h)
+        return src, dst, om
+
+    def get_wedge_list(self, idx) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+        """(src, dst, omega) of the listed hyperwedges (indices in get_wedges order)."""
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        n = idx.shape[0]
+        src = np.zeros(n, np.int32)
+        dst = np.zeros(n, np.int32)
+        om = np.zeros(n, np.int32)
+        _check(self._lib.htri_get_wedge_list(self._h, _ptr(idx), n, _ptr(src), _ptr(dst), _ptr(om)),
+               "htri_get_wedge_list", self._h)
         return src, dst, om
 
     def count_patterns(self, mask: int = 0, per_edge: bool = False, per_wedge: bool = False,

@@ -45,6 +45,10 @@ def check_exact(htri, g, flags=None, wedge_sample=None, nthreads=0, seed=0, wind
     s = G.build_wedges()
     assert np.array_equal(s, o.summary()), (s, o.summary())
     src, dst, om = G.get_wedges()
+    if src.shape[0]:
+        pick = np.random.default_rng(seed).choice(src.shape[0], size=min(50, src.shape[0]), replace=False)
+        ls, ld, lw = G.get_wedge_list(pick)
+        assert np.array_equal(ls, src[pick]) and np.array_equal(ld, dst[pick]) and np.array_equal(lw, om[pick])
     wi, wj, wo = o.wedges()
     lo, hi = np.minimum(src, dst), np.maximum(src, dst)
     got = np.lexsort((hi, lo))
