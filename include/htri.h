@@ -98,6 +98,9 @@ typedef struct {
 #define HTRI_COUNT_INCLUSION_CLASSES 64u /* count only patterns 1-8 (classes    */
                                          /* CCC, TCC, TTC), around the inclusion */
                                          /* hyperwedges; per_wedge must be NULL  */
+#define HTRI_COUNT_OWNER_PROBE 128u  /* probe every partner's whole forward    */
+                                     /* list against its owner's (instead of   */
+                                     /* each owner's rest against the middle)  */
 
 /* Load and normalise a hypergraph (Def. 2.1 and the distinct-hyperedge
  * assumption of Section 2), build E_v (Algorithm 2).
@@ -162,8 +165,8 @@ htri_status htri_get_wedge_list(const htri_graph *g, const int64_t *wedge_idx, i
  *   per_wedge   NULL or int32[|wedges|]: per hyperwedge (htri_get_wedges
  *               order), the number of third hyperedges that close it and
  *               come after dst in prec (all patterns).
- *   out_flags   HTRI_OUTPUT_ON_DEVICE, and at most one of
- *               HTRI_COUNT_NO_WINDOW / HTRI_COUNT_WINDOW_ALWAYS /
+ *   out_flags   HTRI_OUTPUT_ON_DEVICE, HTRI_COUNT_OWNER_PROBE, and at
+ *               most one of HTRI_COUNT_NO_WINDOW / HTRI_COUNT_WINDOW_ALWAYS /
  *               HTRI_COUNT_INCLUSION_CLASSES.  The last counts only the
  *               classes whose hyper-triangles hold an inclusion hyperwedge
  *               (patterns 1-8; Count-CCC, Count-TCC and Count-TTC of
@@ -173,7 +176,14 @@ htri_status htri_get_wedge_list(const htri_graph *g, const int64_t *wedge_idx, i
  *               whole graph or a power of two of them, up to 131072) are
  *               closed by bitmap intersection when the hyperwedges among
  *               them fill at least 1/8 of all pairs (the largest such set);
- *               the counts do not depend on the choice.
+ *               the counts do not depend on the choice.  The other owners
+ *               are closed by hash probing, by default around the middle
+ *               hyperedge: for each hyperwedge (r, j), the entries of N+(r)
+ *               after j are probed against N+(j).  HTRI_COUNT_OWNER_PROBE
+ *               probes each partner's whole N+(j) against N+(r) instead; it
+ *               is also taken when the middle-side lists (about 40 bytes
+ *               per hyperwedge) do not fit in free device memory or hold
+ *               2^32 hyperwedges or more.
  * Errors: HTRI_E_STATE (no wedges yet), HTRI_E_INVALID (unknown flag),
  * HTRI_E_OOM, HTRI_E_DEVICE. */
 htri_status htri_count_patterns(htri_graph *g, uint32_t per_edge_pattern_mask, int64_t counts[21],
@@ -212,14 +222,18 @@ htri_status htri_last_timings(const htri_graph *g, double ms[6]);
 
 /* Work census of the last htri_count_patterns: out[0] = S, the closure
  * stream sum over hyperwedges (r, j) of |N+(j)|; out[1] = entries the
- * probing kernel probed (partner lists are cut to each chunk's rank range);
+ * probing kernel probed (owner-centric: the partners' lists cut to each
+ * chunk's rank range; middle-centric: the entries of N+(r) after j);
  * out[2] = work items; out[3] = 32-bit Omega mask words stored; out[4] =
  * closure blocks launched; out[5] = rows of the dense window (0: none);
  * out[6] = hyperwedges owned inside it; out[7] = S over the owners outside
  * it; out[8] = hyperwedges owned outside it; out[9] = mask words of those;
  * out[10] = 32-bit bitmap words the window closure read; out[11] = window
- * hits enumerated one by one (all but the bulk-counted common-vertex ones). */
-htri_status htri_closure_stats(const htri_graph *g, int64_t out[12]);
+ * hits enumerated one by one (all but the bulk-counted common-vertex ones);
+ * out[12] = 1 if the probing ran middle-centric, 0 if owner-centric;
+ * out[13] = hyperwedges in the middle-side in-list; out[14] = its mask
+ * words; out[15] = hashed entries the probing kernel staged in LDS. */
+htri_status htri_closure_stats(const htri_graph *g, int64_t out[16]);
 
 /* ---------------------------------------------------------------- sampling */
 

@@ -154,6 +154,8 @@ htri_status htri_clear_wedges(htri_graph *h) {
         g.mptr.reset();
         g.fmask.reset();
         g.indeg.reset();
+        g.inpos.reset();
+        g.insnap.reset();
         g.nw = 0;
         g.have_wedges = false;
     });
@@ -208,10 +210,13 @@ htri_status htri_enumerate(htri_graph *h, int32_t pattern, int64_t capacity, int
     });
 }
 
-htri_status htri_closure_stats(const htri_graph *h, int64_t out[12]) {
-    if (!h || !out) return HTRI_E_INVALID;
-    std::memcpy(out, h->g.cstats, sizeof(int64_t) * 12);
-    return HTRI_OK;
+htri_status htri_closure_stats(const htri_graph *hc, int64_t out[16]) {
+    if (!hc || !out) return HTRI_E_INVALID;
+    htri_graph *h = const_cast<htri_graph *>(hc);
+    return run(&h->g, [&] {
+        htri::closure_stream_stats(h->g);
+        std::memcpy(out, h->g.cstats, sizeof(int64_t) * 16);
+    });
 }
 
 htri_status htri_get_wedges(const htri_graph *hc, int32_t *src, int32_t *dst, int32_t *omega) {
@@ -296,7 +301,7 @@ htri_status htri_count_patterns(htri_graph *h, uint32_t per_edge_pattern_mask, i
                                 int64_t *per_edge, int32_t *per_wedge, uint32_t out_flags) {
     if (!h || !counts) return HTRI_E_INVALID;
     if (out_flags & ~(HTRI_OUTPUT_ON_DEVICE | HTRI_COUNT_NO_WINDOW | HTRI_COUNT_WINDOW_ALWAYS |
-                      HTRI_COUNT_INCLUSION_CLASSES))
+                      HTRI_COUNT_INCLUSION_CLASSES | HTRI_COUNT_OWNER_PROBE))
         return HTRI_E_INVALID;
     {
         const uint32_t modes = out_flags & (HTRI_COUNT_NO_WINDOW | HTRI_COUNT_WINDOW_ALWAYS | HTRI_COUNT_INCLUSION_CLASSES);

@@ -44,6 +44,13 @@ __device__ __forceinline__ T gld(const T *p) {
     return *(const __attribute__((address_space(1))) T *)p;
 }
 
+// 16-byte loads through the global address space
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 gld(const uint4 *p) {
+    const u32x4_t v = *(const __attribute__((address_space(1))) u32x4_t *)p;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 // first index in [a, b) whose entry's rank is >= key
 __device__ __forceinline__ int64_t lower_rank(const uint32_t *fadj, int64_t a, int64_t b, uint32_t key,
                                               int wbits) {
@@ -70,6 +77,83 @@ __device__ int triple_common(const int64_t *eptr, const int32_t *emem, int32_t r
         if (z < mx) c++;
     }
     return cnt;
+}
+
+// Omega_jr over e_j's member positions for the hyperwedge (r, j) at position
+// off of N+(r): each vertex of Omega_rj (over e_r's positions) located in
+// e_j's sorted member list jm[0, sj) (LDS) by binary search, or a merge of
+// the two member lists when e_r has no stored mask.
+__device__ void middle_mask(const int64_t *eptr, const int32_t *emem, const int64_t *mptr, const uint32_t *fmask,
+                            int32_t r, int sr, int64_t off, const int32_t *jm, int sj, uint32_t &o0, uint32_t &o1,
+                            uint32_t &o2, uint32_t &o3) {
+    o0 = o1 = o2 = o3 = 0u;
+    auto set = [&](int q) {
+        const uint32_t bit = 1u << (q & 31);
+        const int w = q >> 5;
+        o0 |= w == 0 ? bit : 0u;
+        o1 |= w == 1 ? bit : 0u;
+        o2 |= w == 2 ? bit : 0u;
+        o3 |= w == 3 ? bit : 0u;
+    };
+    const int64_t rb = gld(eptr + r);
+    const int Wr = mask_words(sr);
+    if (Wr > 0) {
+        const int64_t mo = gld(mptr + r) + off * Wr;
+        for (int w = 0; w < Wr; w++) {
+            uint32_t x = gld(fmask + mo + w);
+            while (x) {
+                const int b = __ffs(x) - 1;
+                x &= x - 1;
+                const int32_t v = gld(emem + rb + w * 32 + b);
+                int lo = 0, hi = sj;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (jm[mid] < v) lo = mid + 1; else hi = mid;
+                }
+                if (lo < sj && jm[lo] == v) set(lo);
+            }
+        }
+    } else {
+        int a = 0, b = 0;
+        while (a < sr && b < sj) {
+            const int32_t va = gld(emem + rb + a), vb = jm[b];
+            if (va == vb) {
+                set(b);
+                a++;
+                b++;
+            } else if (va < vb) {
+                a++;
+            } else {
+                b++;
+            }
+        }
+    }
+}
+
+// Omega_jr of an in-list entry: the shared vertex's position in jm (one
+// bit), or middle_mask() when the entry holds no single vertex
+__device__ __forceinline__ void entry_mask(const GraphDesc &G, const uint4 &E, int wbits, const int32_t *jm, int sj,
+                                           uint32_t &o0, uint32_t &o1, uint32_t &o2, uint32_t &o3) {
+    const uint32_t wmask = (1u << wbits) - 1;
+    if (E.z != kInNoVertex) {
+        const int32_t v = (int32_t)E.z;
+        int lo = 0, hi = sj;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (jm[mid] < v) lo = mid + 1; else hi = mid;
+        }
+        const bool in = lo < sj && jm[lo] == v;
+        const uint32_t bit = in ? 1u << (lo & 31) : 0u;
+        const int w = lo >> 5;
+        o0 = w == 0 ? bit : 0u;
+        o1 = w == 1 ? bit : 0u;
+        o2 = w == 2 ? bit : 0u;
+        o3 = w == 3 ? bit : 0u;
+    } else {
+        const int32_t r = (int32_t)(E.w >> wbits);
+        const int64_t off = (int64_t)E.x - gld(G.fptr + r);
+        middle_mask(G.eptr, G.emem, G.mptr, G.fmask, r, (int)(E.w & wmask), off, jm, sj, o0, o1, o2, o3);
+    }
 }
 
 __device__ __forceinline__ uint32_t region_mask(int si, int sj, int sk, int wij, int wik, int wjk, int g) {
@@ -263,21 +347,29 @@ struct CloseBlockLds {
     uint32_t seg_cj[PW ? JP : 1];
     uint32_t seg_cjm[PE ? JP : 1];
 };
+// Owner-centric wave items take the partner data from the chunk arrays
+// (partner q is entry q of N+(r)); middle-centric ones keep it apart in
+// p_sm / p_mx / p_ent, with p_ent = (rank of r) << wbits | omega_jr.
+template <bool MID>
 struct CloseWaveLds {
     uint2 tab[4 * kWaveOwnerMax];
-    uint2 ent_sm[kWaveOwnerMax];                       // (|e_k|, Omega_rk word 0); also the partner's data
+    uint2 ent_sm[kWaveOwnerMax];                       // (|e_k|, Omega word 0 of the hashed entry)
     uint32_t ent_mx[kWaveOwnerMax * (kMaskWordsMax - 1)];
     uint32_t ent_ck[kWaveOwnerMax];
     int64_t src[kWaveOwnerMax];                        // partner segment start minus its stream offset
-    uint32_t ent[kWaveOwnerMax];                       // packed entry (rank, omega) of N+(r)
+    uint32_t ent[kWaveOwnerMax];                       // packed entry (rank, omega) of the hashed list
     int32_t incl[kWaveOwnerMax];                       // end of each partner segment in the stream
     uint32_t cj[kWaveOwnerMax];
     uint32_t cjm[kWaveOwnerMax];
+    uint2 p_sm[MID ? kWaveOwnerMax : 2];               // (|e_r|, Omega_jr word 0)
+    uint32_t p_mx[MID ? kWaveOwnerMax * (kMaskWordsMax - 1) : 4];
+    uint32_t p_ent[MID ? kWaveOwnerMax : 4];
+    int32_t jmem[MID ? 32 * kMaskWordsMax : 4];        // e_j's members (hyperedges with stored masks)
 };
-template <int CAP, int JP, bool PE, bool PW>
+template <int CAP, int JP, bool PE, bool PW, bool MID>
 union CloseLds {
     CloseBlockLds<CAP, JP, PE, PW> b;
-    CloseWaveLds w[kBlock / kWave];
+    CloseWaveLds<MID> w[kBlock / kWave];
 };
 
 // Order this wave's earlier LDS accesses before its later ones, across lanes
@@ -288,12 +380,20 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-template <int CAP, int JP, bool PER_EDGE, bool PER_WEDGE>
+// MID = false: owner-centric items (owner r hashed, each partner's N+(j)
+// streamed).  MID = true: middle-centric items (the middle j's N+(j)
+// hashed, the rest of N+(r) after j streamed for each hyperwedge (r, j) of
+// j's in-list); a hit k closes r < j < k.  The classification is the same
+// with the roles (r, j, k) read as (j, r, k): sizes |e_j|, |e_r|, |e_k|,
+// omegas omega_jr (segment), omega_jk (hashed entry), omega_rk (streamed
+// entry), and g = popcount(Omega_jr & Omega_jk) over e_j's member
+// positions; the region table is invariant under relabelling.
+template <int CAP, int JP, bool PER_EDGE, bool PER_WEDGE, bool MID>
 __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
     static_assert(JP <= kBlock, "one thread per partner");
     constexpr int HMAX = 4 * CAP;
-    static_assert(sizeof(CloseWaveLds) % 16 == 0, "wave slices keep the table 16-byte aligned");
-    __shared__ __align__(16) CloseLds<CAP, JP, PER_EDGE, PER_WEDGE> L;
+    static_assert(sizeof(CloseWaveLds<MID>) % 16 == 0, "wave slices keep the table 16-byte aligned");
+    __shared__ __align__(16) CloseLds<CAP, JP, PER_EDGE, PER_WEDGE, MID> L;
     uint2 *tab = L.b.tab;
     uint2 *ent_sm = L.b.ent_sm;
     uint32_t *ent_mx = L.b.ent_mx;
@@ -307,6 +407,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
     uint32_t *seg_cjm = L.b.seg_cjm;
     (void)HMAX;
     __shared__ uint8_t lut[128];
+    __shared__ int32_t s_jmem[MID ? 32 * kMaskWordsMax : 1];   // the middle's members
     __shared__ int64_t sh_item;
     __shared__ int64_t sh_scan[kBlock / kWave + 1];
 
@@ -316,7 +417,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
     if (tid < 128) lut[tid] = A.lut[tid];
     unsigned long long wcnt = 0;     // lane p: this wave's count of pattern p (p != 9)
     unsigned long long c9 = 0;       // this lane's count of the common-vertex pattern
-    unsigned long long all_probes = 0;
+    unsigned long long all_probes = 0, all_staged = 0;
     int cur_g = -1;
 
     for (;;) {
@@ -339,7 +440,22 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
         const int32_t r = item.r;
         const int64_t base = gld(G.fptr + r);
         const int32_t d = (int32_t)(gld(G.fptr + r + 1) - base);
-        const bool single = item.cb == 0 && item.ce == d && item.jb == 0 && item.je == d - 1;
+        // whole_chunk: the chunk is all of the hashed list (no rank cut);
+        // whole_in: the item holds every partner of the hashed list
+        const bool whole_chunk = item.cb == 0 && item.ce == d;
+        bool whole_in = item.jb == 0 && item.je == d - 1;
+        int64_t ibase = 0;
+        if (MID) {
+            ibase = gld(G.iptr + r);
+            whole_in = item.jb == 0 && (int64_t)item.je == gld(G.iptr + r + 1) - ibase;
+        }
+        const bool single = whole_chunk && whole_in;
+        // rank of the hyperedge of partner segment q (the member merge of
+        // hashed hyperedges without a stored mask)
+        auto seg_rank = [&](int q) -> int32_t {
+            if (MID) return (int32_t)(gld(G.inl + ibase + item.jb + q).w >> wbits);
+            return (int32_t)(gld(G.fadj + base + item.jb + q) >> wbits);
+        };
         const int si = gld(G.esize + r);
         const int W = mask_words(si);
         const int64_t mbase = gld(G.mptr + r);
@@ -351,6 +467,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
         const uint32_t hi = gld(G.fadj + base + item.ce - 1) >> wbits;
 
         for (int s = tid; s < H; s += kBlock) tab[s] = make_uint2(0u, kEmptyPos);
+        if (MID && W > 0) {
+            const int64_t jb0 = gld(G.eptr + r);
+            for (int t = tid; t < si; t += kBlock) s_jmem[t] = gld(G.emem + jb0 + t);
+        }
         __syncthreads();
         // stage the chunk
         for (int q = tid; q < cl; q += kBlock) {
@@ -368,7 +488,35 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
         // partner segments: N+(j) cut to the chunk's rank range
         const int nseg = item.je - item.jb;
         int64_t len = 0;
-        if (tid < nseg) {
+        int64_t my_wedge = 0;          // MID: the hyperwedge (r, j) of this thread's segment
+        if (MID && tid < nseg) {
+            const uint4 E = gld(G.inl + ibase + item.jb + tid);
+            const int64_t i = (int64_t)E.x;
+            int64_t a = i + 1, b = a + (int64_t)(E.y >> wbits);
+            if (!whole_chunk) {
+                a = lower_rank(G.fadj, a, b, lo, wbits);
+                b = lower_rank(G.fadj, a, b, hi + 1, wbits);
+            }
+            len = b - a;
+            seg_src[tid] = a;
+            const uint32_t om = E.y & wmask;
+            const uint32_t sz = E.w & wmask;
+            seg_size[tid] = sz;
+            const bool fj = (W == 1) && ((uint32_t)si > om) && (sz > om);
+            seg_om[tid] = om | (fj ? 0x80000000u : 0u);
+            if (W > 0) {
+                uint32_t o0, o1, o2, o3;
+                entry_mask(G, E, wbits, s_jmem, si, o0, o1, o2, o3);
+                seg_mask[tid * kMaskWordsMax + 0] = o0;
+                if (W > 1) seg_mask[tid * kMaskWordsMax + 1] = o1;
+                if (W > 2) seg_mask[tid * kMaskWordsMax + 2] = o2;
+                if (W > 3) seg_mask[tid * kMaskWordsMax + 3] = o3;
+            }
+            if (PER_WEDGE) seg_cj[tid] = 0;
+            if (PER_EDGE) seg_cjm[tid] = 0;
+            my_wedge = i;
+        }
+        if (!MID && tid < nseg) {
             const int pj = item.jb + tid;
             const uint32_t jent = gld(G.fadj + base + pj);
             const uint32_t j = jent >> wbits;
@@ -416,6 +564,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
         __syncthreads();
         const int64_t total = seg_pre[kBlock];
         all_probes += (unsigned long long)total;
+        all_staged += (unsigned long long)cl;
 
         // Partner-list entries go through probe_tile(); both loops below
         // keep the next tile's loads in flight while the current tile is
@@ -476,7 +625,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                 const uint32_t m2 = W > 2 ? seg_mask[qd * kMaskWordsMax + 2] : 0u;
                 const uint32_t m3 = W > 3 ? seg_mask[qd * kMaskWordsMax + 3] : 0u;
                 const bool fastd = (W == 1) && (si > wd) && (sjd > wd);
-                const int32_t jr = (W == 0) ? (int32_t)(gld(G.fadj + base + item.jb + qd) >> wbits) : 0;
+                const int32_t jr = (W == 0) ? seg_rank(qd) : 0;
                 const JParams Jd{sjd, wd, fastd, m0, m1, m2, m3, jr};
                 bool hit[kUnroll], mhit[kUnroll];
                 uint32_t po[kUnroll];
@@ -602,7 +751,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                     J.m1 = W > 1 ? seg_mask[qq * kMaskWordsMax + 1] : 0u;
                     J.m2 = W > 2 ? seg_mask[qq * kMaskWordsMax + 2] : 0u;
                     J.m3 = W > 3 ? seg_mask[qq * kMaskWordsMax + 3] : 0u;
-                    J.jr = (W == 0) ? (int32_t)(gld(G.fadj + base + item.jb + qq) >> wbits) : 0;
+                    J.jr = (W == 0) ? seg_rank(qq) : 0;
                     return J;
                 };
                 probe_tile<PER_EDGE>(tab, hbits, wbits, wmask, entA, valA, fwij, fm0, ffast, jf, ent_sm, ent_mx, ent_ck,
@@ -637,10 +786,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
         }
         __syncthreads();
         // per-wedge counters (single-graph launches only)
+        // A middle-centric segment (one hyperwedge) meets each chunk once;
+        // an owner-centric partner meets every chunk of its owner.
         if (PER_WEDGE || PER_EDGE) {
+            const bool seg_direct = MID ? whole_chunk : single;
+            const bool ent_direct = MID ? (whole_in && (int64_t)r < A.kdirect_end) : single;
             if (tid < nseg) {
-                const int64_t e = base + item.jb + tid;
-                if (single) {
+                const int64_t e = MID ? my_wedge : base + item.jb + tid;
+                if (seg_direct) {
                     if (PER_WEDGE) A.cwj[e] = seg_cj[tid];
                     if (PER_EDGE) A.cwjm[e] = seg_cjm[tid];
                 } else {
@@ -651,20 +804,25 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
             if (PER_EDGE) {
                 for (int qq = tid; qq < cl; qq += kBlock) {
                     const int64_t e = base + item.cb + qq;
-                    if (single) A.cwkm[e] = ent_ck[qq];
+                    if (ent_direct) A.cwkm[e] = ent_ck[qq];
                     else if (ent_ck[qq]) atomicAdd(&A.cwkm[e], ent_ck[qq]);
                 }
             }
         }
     }
     if (tid == 0 && all_probes) atomicAdd(A.probes, all_probes);
+    if (tid == 0 && all_staged && A.staged) atomicAdd(A.staged, all_staged);
 
     // Single-owner items, one wave each, in the wave's own LDS slice: the
     // block items are drained and every wave of the block has passed the
     // loop's last barrier, so the block layout is dead.  No block barrier
     // from here on.
-    CloseWaveLds &Wl = L.w[wave];
-    unsigned long long wprobes = 0;
+    CloseWaveLds<MID> &Wl = L.w[wave];
+    // partner data: the chunk's own entries (owner-centric) or the in-list's
+    const uint2 *p_sm = MID ? Wl.p_sm : Wl.ent_sm;
+    const uint32_t *p_ent = MID ? Wl.p_ent : Wl.ent;
+    const uint32_t *p_mx = MID ? Wl.p_mx : Wl.ent_mx;
+    unsigned long long wprobes = 0, wstaged = 0;
     for (;;) {
         unsigned int c = 0;
         if (lane == 0) c = atomicAdd(A.wqueue, 1u);
@@ -680,7 +838,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
         const uint32_t wmask = (1u << wbits) - 1;
         const int32_t r = item.r;
         const int64_t base = gld(G.fptr + r);
-        const int d = item.ce;                 // all of N+(r); partners are entries 0 .. d-2
+        const int d = item.ce;                 // all of the hashed list N+(r)
+        const int npart = MID ? item.je : d - 1;   // partners: in-list entries, or entries 0 .. d-2
         const int si = gld(G.esize + r);
         const int W = mask_words(si);
         const int64_t mbase = gld(G.mptr + r);
@@ -689,10 +848,18 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
         const int H = 1 << hbits;              // <= 4 * kWaveOwnerMax
         wave_lds_sync();                       // the previous owner's reads are done
         for (int t = lane; t < H; t += kWave) Wl.tab[t] = make_uint2(0u, kEmptyPos);
+        if (MID && W > 0) {
+            const int64_t jb0 = gld(G.eptr + r);
+            for (int t = lane; t < si; t += kWave) Wl.jmem[t] = gld(G.emem + jb0 + t);
+        }
         wave_lds_sync();
-        // lane q holds entry q of N+(r): the third hyperedge k = j_q of the
-        // chunk role and the partner j_q of the wedge (r, j_q)
+        // lane q holds entry q of the hashed list (owner-centric: also the
+        // partner j_q of the wedge (r, j_q)) and, middle-centric, entry q of
+        // the in-list
         int64_t len = 0, a = 0;
+        int64_t my_wedge = 0;
+        Wl.cj[lane] = 0;
+        Wl.cjm[lane] = 0;
         if (lane < d) {
             const uint32_t ent = gld(G.fadj + base + lane);
             const uint32_t k = ent >> wbits;
@@ -701,15 +868,27 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
             for (int w = 1; w < W; w++) Wl.ent_mx[lane * (kMaskWordsMax - 1) + (w - 1)] = gld(G.fmask + mo + w);
             Wl.ent[lane] = ent;
             if (PER_EDGE) Wl.ent_ck[lane] = 0;
-            Wl.cj[lane] = 0;
-            Wl.cjm[lane] = 0;
             uint32_t slot = hslot(k, hbits - 1) * 2;
             while (atomicCAS(&Wl.tab[slot].y, kEmptyPos, (uint32_t)lane) != kEmptyPos) slot = (slot + 1) & (H - 1);
             Wl.tab[slot].x = ent;
-            if (lane < d - 1) {
+            if (!MID && lane < d - 1) {
                 a = gld(G.fptr + k);
                 len = gld(G.fptr + k + 1) - a;
             }
+        }
+        if (MID && lane < npart) {
+            const uint4 E = gld(G.inl + gld(G.iptr + r) + lane);
+            const int64_t i = (int64_t)E.x;
+            a = i + 1;
+            len = (int64_t)(E.y >> wbits);
+            uint32_t o0 = 0u, o1 = 0u, o2 = 0u, o3 = 0u;
+            if (W > 0) entry_mask(G, E, wbits, Wl.jmem, si, o0, o1, o2, o3);
+            Wl.p_sm[lane] = make_uint2(E.w & wmask, o0);
+            Wl.p_mx[lane * (kMaskWordsMax - 1) + 0] = o1;
+            Wl.p_mx[lane * (kMaskWordsMax - 1) + 1] = o2;
+            Wl.p_mx[lane * (kMaskWordsMax - 1) + 2] = o3;
+            Wl.p_ent[lane] = (E.w & ~wmask) | (E.y & wmask);   // (r << wbits) | omega_rj
+            my_wedge = i;
         }
         int64_t incl = len;
 #pragma unroll
@@ -717,13 +896,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
             const int64_t u = __shfl_up(incl, o, kWave);
             if (lane >= o) incl += u;
         }
-        const int64_t total = __shfl(incl, kWave - 1, kWave);   // lanes >= d-1 add nothing
-        if (lane < d - 1) {
+        const int64_t total = __shfl(incl, kWave - 1, kWave);   // lanes >= npart add nothing
+        if (lane < npart) {
             Wl.incl[lane] = (int32_t)incl;
             Wl.src[lane] = a - (incl - len);
         }
         wave_lds_sync();
         wprobes += (unsigned long long)total;
+        wstaged += (unsigned long long)d;
         // the partner lists end to end, kUnroll consecutive entries per lane
         int qa = 0;                            // search cursor (monotone per lane)
         int q = -1;                            // segment whose counters this lane holds
@@ -738,7 +918,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                 seg4[u] = -1;
                 ent4[u] = 0u;
                 if (f < wtotal) {
-                    while (Wl.incl[qa] <= f) qa++;     // ends at a segment <= d-2 since f < total
+                    while (Wl.incl[qa] <= f) qa++;     // ends at a segment < npart since f < total
                     seg4[u] = qa;
                     ent4[u] = gld(G.fadj + Wl.src[qa] + f);
                 }
@@ -759,8 +939,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                     const int qq = seg4[u] < 0 ? 0 : seg4[u];
                     if (qq != qc) {
                         qc = qq;
-                        const uint2 jsm = Wl.ent_sm[qq];
-                        cw = (int)(Wl.ent[qq] & wmask);
+                        const uint2 jsm = p_sm[qq];
+                        cw = (int)(p_ent[qq] & wmask);
                         cm = jsm.y;
                         cf = (W == 1) && (si > cw) && ((int)jsm.x > cw);
                     }
@@ -771,16 +951,16 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
             }
             auto jf = [&](int u) {
                 const int qq = seg4[u] < 0 ? 0 : seg4[u];
-                const uint2 jsm = Wl.ent_sm[qq];
-                const uint32_t jent = Wl.ent[qq];
+                const uint2 jsm = p_sm[qq];
+                const uint32_t jent = p_ent[qq];
                 JParams J;
                 J.sj = (int)jsm.x;
                 J.wij = (int)(jent & wmask);
                 J.fast = (W == 1) && (si > J.wij) && (J.sj > J.wij);
                 J.m0 = jsm.y;
-                J.m1 = W > 1 ? Wl.ent_mx[qq * (kMaskWordsMax - 1) + 0] : 0u;
-                J.m2 = W > 2 ? Wl.ent_mx[qq * (kMaskWordsMax - 1) + 1] : 0u;
-                J.m3 = W > 3 ? Wl.ent_mx[qq * (kMaskWordsMax - 1) + 2] : 0u;
+                J.m1 = W > 1 ? p_mx[qq * (kMaskWordsMax - 1) + 0] : 0u;
+                J.m2 = W > 2 ? p_mx[qq * (kMaskWordsMax - 1) + 1] : 0u;
+                J.m3 = W > 3 ? p_mx[qq * (kMaskWordsMax - 1) + 2] : 0u;
                 J.jr = (int32_t)(jent >> wbits);
                 return J;
             };
@@ -810,14 +990,19 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
         }
         wave_lds_sync();
         if (PER_WEDGE || PER_EDGE) {
-            if (lane < d - 1) {
-                if (PER_WEDGE) A.cwj[base + lane] = Wl.cj[lane];
-                if (PER_EDGE) A.cwjm[base + lane] = Wl.cjm[lane];
+            if (lane < npart) {
+                const int64_t e = MID ? my_wedge : base + lane;
+                if (PER_WEDGE) A.cwj[e] = Wl.cj[lane];
+                if (PER_EDGE) A.cwjm[e] = Wl.cjm[lane];
             }
-            if (PER_EDGE && lane < d) A.cwkm[base + lane] = Wl.ent_ck[lane];
+            if (PER_EDGE && lane < d) {
+                if (!MID || (int64_t)r < A.kdirect_end) A.cwkm[base + lane] = Wl.ent_ck[lane];
+                else if (Wl.ent_ck[lane]) atomicAdd(&A.cwkm[base + lane], Wl.ent_ck[lane]);
+            }
         }
     }
     if (lane == 0 && wprobes) atomicAdd(A.probes, wprobes);
+    if (lane == 0 && wstaged && A.staged) atomicAdd(A.staged, wstaged);
     if (cur_g >= 0) flush_wave_counts(wcnt, c9, A.counts, cur_g, lane);
 }
 
@@ -948,25 +1133,26 @@ __global__ void k_rank_to_norm_u64(const unsigned long long *t, const int32_t *n
         out[norm_of_rank[r]] = (int64_t)t[r];
 }
 
-template <int CAP, int JP, bool PE, bool PW>
+template <int CAP, int JP, bool PE, bool PW, bool MID>
 int occ_blocks() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_close<CAP, JP, PE, PW>, kBlock, 0) != hipSuccess || nb < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_close<CAP, JP, PE, PW, MID>, kBlock, 0) != hipSuccess ||
+        nb < 1)
         nb = 1;
     return nb;
 }
 
-template <int CAP, int JP>
+template <int CAP, int JP, bool MID>
 struct CloseVariants {
     static int blocks(bool pe, bool pw) {
-        return pe ? (pw ? occ_blocks<CAP, JP, true, true>() : occ_blocks<CAP, JP, true, false>())
-                  : (pw ? occ_blocks<CAP, JP, false, true>() : occ_blocks<CAP, JP, false, false>());
+        return pe ? (pw ? occ_blocks<CAP, JP, true, true, MID>() : occ_blocks<CAP, JP, true, false, MID>())
+                  : (pw ? occ_blocks<CAP, JP, false, true, MID>() : occ_blocks<CAP, JP, false, false, MID>());
     }
     static void launch(bool pe, bool pw, const CloseArgs &a, int nb, hipStream_t s) {
-        if (pe && pw) hipLaunchKernelGGL((k_close<CAP, JP, true, true>), dim3(nb), dim3(kBlock), 0, s, a);
-        else if (pe) hipLaunchKernelGGL((k_close<CAP, JP, true, false>), dim3(nb), dim3(kBlock), 0, s, a);
-        else if (pw) hipLaunchKernelGGL((k_close<CAP, JP, false, true>), dim3(nb), dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL((k_close<CAP, JP, false, false>), dim3(nb), dim3(kBlock), 0, s, a);
+        if (pe && pw) hipLaunchKernelGGL((k_close<CAP, JP, true, true, MID>), dim3(nb), dim3(kBlock), 0, s, a);
+        else if (pe) hipLaunchKernelGGL((k_close<CAP, JP, true, false, MID>), dim3(nb), dim3(kBlock), 0, s, a);
+        else if (pw) hipLaunchKernelGGL((k_close<CAP, JP, false, true, MID>), dim3(nb), dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL((k_close<CAP, JP, false, false, MID>), dim3(nb), dim3(kBlock), 0, s, a);
         HTRI_LAUNCH_CHECK();
     }
 };
@@ -977,20 +1163,29 @@ bool valid_config(const CloseConfig &c) {
     return (c.cap == 256 || c.cap == 512) && (c.jp == 128 || c.jp == 256);
 }
 
-int close_blocks_per_cu(const CloseConfig &c, bool pe, bool pw) {
-    if (c.cap == 256 && c.jp == 128) return CloseVariants<256, 128>::blocks(pe, pw);
-    if (c.cap == 256 && c.jp == 256) return CloseVariants<256, 256>::blocks(pe, pw);
-    if (c.cap == 512 && c.jp == 128) return CloseVariants<512, 128>::blocks(pe, pw);
-    if (c.cap == 512 && c.jp == 256) return CloseVariants<512, 256>::blocks(pe, pw);
+int close_blocks_per_cu(const CloseConfig &c, bool pe, bool pw, bool mid) {
+    if (mid) {
+        if (c.cap == 512 && c.jp == 256) return CloseVariants<512, 256, true>::blocks(pe, pw);
+        fail(HTRI_E_INVALID, "middle-centric closure runs the default configuration only");
+    }
+    if (c.cap == 256 && c.jp == 128) return CloseVariants<256, 128, false>::blocks(pe, pw);
+    if (c.cap == 256 && c.jp == 256) return CloseVariants<256, 256, false>::blocks(pe, pw);
+    if (c.cap == 512 && c.jp == 128) return CloseVariants<512, 128, false>::blocks(pe, pw);
+    if (c.cap == 512 && c.jp == 256) return CloseVariants<512, 256, false>::blocks(pe, pw);
     fail(HTRI_E_INVALID, "unsupported closure configuration");
     return 0;
 }
 
-void launch_close_kernel(const CloseConfig &c, bool pe, bool pw, const CloseArgs &a, int nb, hipStream_t s) {
-    if (c.cap == 256 && c.jp == 128) return CloseVariants<256, 128>::launch(pe, pw, a, nb, s);
-    if (c.cap == 256 && c.jp == 256) return CloseVariants<256, 256>::launch(pe, pw, a, nb, s);
-    if (c.cap == 512 && c.jp == 128) return CloseVariants<512, 128>::launch(pe, pw, a, nb, s);
-    if (c.cap == 512 && c.jp == 256) return CloseVariants<512, 256>::launch(pe, pw, a, nb, s);
+void launch_close_kernel(const CloseConfig &c, bool pe, bool pw, const CloseArgs &a, int nb, hipStream_t s,
+                         bool mid) {
+    if (mid) {
+        if (c.cap == 512 && c.jp == 256) return CloseVariants<512, 256, true>::launch(pe, pw, a, nb, s);
+        fail(HTRI_E_INVALID, "middle-centric closure runs the default configuration only");
+    }
+    if (c.cap == 256 && c.jp == 128) return CloseVariants<256, 128, false>::launch(pe, pw, a, nb, s);
+    if (c.cap == 256 && c.jp == 256) return CloseVariants<256, 256, false>::launch(pe, pw, a, nb, s);
+    if (c.cap == 512 && c.jp == 128) return CloseVariants<512, 128, false>::launch(pe, pw, a, nb, s);
+    if (c.cap == 512 && c.jp == 256) return CloseVariants<512, 256, false>::launch(pe, pw, a, nb, s);
     fail(HTRI_E_INVALID, "unsupported closure configuration");
 }
 
@@ -1007,16 +1202,114 @@ GraphDesc graph_desc(const Graph &g) {
     return d;
 }
 
-void build_items(Graph &g, int32_t gid, const CloseConfig &cfg, ItemLists &out, int64_t owner_end) {
+// ---------------------------------------------------------------- in-list
+
+namespace {
+
+// number of in-list entries of each middle j: all its earlier neighbours
+// below the window start w0, else (j >= w0) the snapshot of its count taken
+// when the owners below w0 were done
+__global__ void k_inlist_counts(const uint32_t *indeg, const uint32_t *snap, int64_t top0, int64_t w0, int64_t m,
+                                int64_t *cnt) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += (int64_t)gridDim.x * blockDim.x)
+        cnt[j] = j < w0 ? (int64_t)indeg[j] : (int64_t)snap[j - top0];
+}
+
+// scatter every hyperwedge (r, j), r < owner_end, to j's in-list at its slot
+// (one InEntry, see the header); one wave per owner.  A slot outside j's
+// range sets *bad instead.
+__global__ void k_inlist_fill(const int64_t *fptr, const uint32_t *fadj, int wbits, int64_t owner_end,
+                              const int32_t *esize, const int64_t *eptr, const int32_t *emem, const int64_t *mptr,
+                              const uint32_t *fmask, const int64_t *iptr, const uint32_t *inpos, uint4 *inl,
+                              unsigned int *bad) {
+    const uint32_t wmask = (1u << wbits) - 1;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; r < owner_end; r += nwaves) {
+        const int64_t b = fptr[r], e = fptr[r + 1];
+        const int sr = esize[r];
+        const int Wr = mask_words(sr);
+        const int64_t mb = mptr[r], rb = eptr[r];
+        for (int64_t q = b + lane; q < e; q += kWave) {
+            const uint32_t ent = fadj[q];
+            const uint32_t j = ent >> wbits, om = ent & wmask;
+            uint32_t v = kInNoVertex;
+            if (om == 1u && Wr > 0) {
+                const int64_t mo = mb + (q - b) * Wr;
+                for (int w = 0; w < Wr; w++) {
+                    const uint32_t x = fmask[mo + w];
+                    if (x) v = (uint32_t)emem[rb + w * 32 + __ffs(x) - 1];
+                }
+            }
+            const int64_t slot = iptr[j] + inpos[q];
+            if (slot < iptr[j + 1]) {
+                inl[slot] = make_uint4((uint32_t)q, ((uint32_t)(e - q - 1) << wbits) | om, v,
+                                       ((uint32_t)r << wbits) | (uint32_t)sr);
+            } else {
+                atomicOr(bad, 1u);
+            }
+        }
+    }
+}
+
+// Middle-centric work items per middle j (at least one forward entry and one
+// in-list entry): wcnt = 1 for a middle closed by one wave (at most
+// kWaveOwnerMax forward entries and in-list entries, and at most
+// kWaveStreamMax streamed entries), else one block item per chunk of N+(j)
+// and piece of jp in-list entries.
+__global__ void k_item_counts_mid(const int64_t *fptr, const int64_t *iptr, const uint4 *inl, int wbits, int64_t m,
+                                  int cap, int jp, int64_t *cnt, int64_t *wcnt) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t d = fptr[j + 1] - fptr[j];
+        const int64_t nin = iptr[j + 1] - iptr[j];
+        int64_t c = 0;
+        bool wave = false;
+        if (d >= 1 && nin >= 1) {
+            if (d <= kWaveOwnerMax && nin <= kWaveOwnerMax) {
+                int64_t sz = 0;
+                for (int64_t p = iptr[j]; p < iptr[j + 1]; p++) sz += (int64_t)(inl[p].y >> wbits);
+                wave = sz <= kWaveStreamMax;
+            }
+            if (!wave) c = ((d + cap - 1) / cap) * ((nin + jp - 1) / jp);
+        }
+        cnt[j] = c;
+        wcnt[j] = wave ? 1 : 0;
+    }
+}
+
+__global__ void k_item_fill_mid(const int64_t *fptr, const int64_t *iptr, int64_t m, int cap, int jp, int32_t gid,
+                                const int64_t *ioff, const int64_t *woff, Item *items, Item *witems) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t d = fptr[j + 1] - fptr[j];
+        const int64_t nin = iptr[j + 1] - iptr[j];
+        if (d < 1 || nin < 1) continue;
+        if (woff[j + 1] != woff[j]) {
+            witems[woff[j]] = Item{gid, (int32_t)j, 0, (int32_t)d, 0, (int32_t)nin};
+            continue;
+        }
+        int64_t o = ioff[j];
+        for (int64_t cb = 0; cb < d; cb += cap) {
+            const int64_t ce = cb + cap < d ? cb + cap : d;
+            for (int64_t jb = 0; jb < nin; jb += jp)
+                items[o++] = Item{gid, (int32_t)j, (int32_t)cb, (int32_t)ce, (int32_t)jb,
+                                  (int32_t)(jb + jp < nin ? jb + jp : nin)};
+        }
+    }
+}
+
+int64_t read_i64(const int64_t *p, hipStream_t s) {
+    int64_t v = 0;
+    HTRI_HIP(hipMemcpyAsync(&v, p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HTRI_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+// scan the per-owner item counts, allocate the lists and let fill() write them
+template <typename F>
+void items_from_counts(Graph &g, DBuf<int64_t> &icnt, DBuf<int64_t> &wcnt, ItemLists &out, F fill) {
     hipStream_t s = g.stream;
     Allocator &A = g.al;
     const int64_t m = g.m;
-    DBuf<int64_t> icnt(A, m + 1), wcnt(A, m + 1);
-    if (m > 0) {
-        hipLaunchKernelGGL(k_item_counts, dim3(grid_for(m, 256)), dim3(256), 0, s, g.fptr.p, g.fadj.p, g.wbits, m,
-                           owner_end, cfg.cap, cfg.jp, icnt.p, wcnt.p);
-        HTRI_LAUNCH_CHECK();
-    }
     scan_exclusive_i64(A, icnt.p, icnt.p, m, icnt.p + m, s);
     scan_exclusive_i64(A, wcnt.p, wcnt.p, m, wcnt.p + m, s);
     int64_t tot[2] = {0, 0};
@@ -1030,12 +1323,88 @@ void build_items(Graph &g, int32_t gid, const CloseConfig &cfg, ItemLists &out, 
     if (out.nblock >= limit || out.nwave >= limit) fail(HTRI_E_UNSUPPORTED, "too many work items");
     out.block.alloc(A, out.nblock);
     out.wave.alloc(A, out.nwave);
-    if (m > 0 && out.nblock + out.nwave > 0) {
+    if (m > 0 && out.nblock + out.nwave > 0) fill();
+    HTRI_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+void build_items(Graph &g, int32_t gid, const CloseConfig &cfg, ItemLists &out, int64_t owner_end) {
+    hipStream_t s = g.stream;
+    const int64_t m = g.m;
+    DBuf<int64_t> icnt(g.al, m + 1), wcnt(g.al, m + 1);
+    if (m > 0) {
+        hipLaunchKernelGGL(k_item_counts, dim3(grid_for(m, 256)), dim3(256), 0, s, g.fptr.p, g.fadj.p, g.wbits, m,
+                           owner_end, cfg.cap, cfg.jp, icnt.p, wcnt.p);
+        HTRI_LAUNCH_CHECK();
+    }
+    items_from_counts(g, icnt, wcnt, out, [&] {
         hipLaunchKernelGGL(k_item_fill, dim3(grid_for(m, 256)), dim3(256), 0, s, g.fptr.p, m, owner_end, cfg.cap,
                            cfg.jp, gid, icnt.p, wcnt.p, out.block.p, out.wave.p);
         HTRI_LAUNCH_CHECK();
+    });
+}
+
+int64_t inlist_bytes(Graph &g, int64_t owner_end) {
+    const int64_t n = owner_end > 0 ? read_i64(g.fptr.p + owner_end, g.stream) : 0;
+    // one 16-byte entry per hyperwedge, offsets and counts, item counts
+    return n * 16 + (g.m + 1) * 40;
+}
+
+// The in-list for owners below owner_end (m, or one of the window's
+// possible starts).
+void build_inlist(Graph &g, int64_t owner_end, InList &out) {
+    hipStream_t s = g.stream;
+    Allocator &A = g.al;
+    const int64_t m = g.m;
+    const int64_t n = owner_end > 0 ? read_i64(g.fptr.p + owner_end, s) : 0;
+    if (n >= (int64_t)UINT32_MAX) fail(HTRI_E_UNSUPPORTED, "in-list beyond 2^32 hyperwedges");
+    int snap = -1;
+    if (owner_end < m)
+        for (int k = 0; k < kWindowStarts; k++)
+            if (window_start(m, k) == owner_end) snap = k;
+    if (owner_end < m && snap < 0) fail(HTRI_E_UNSUPPORTED, "in-list for a window start the builder did not mark");
+    const int64_t top0 = g.insnap_top;
+    if (2 * g.wbits > 32) fail(HTRI_E_UNSUPPORTED, "in-list packing needs hyperedge sizes below 2^16");
+    out.n = n;
+    out.inl.alloc(A, n);
+    out.iptr.alloc(A, m + 1);
+    if (m > 0) {
+        hipLaunchKernelGGL(k_inlist_counts, dim3(grid_for(m, 256)), dim3(256), 0, s, g.indeg.p,
+                           snap >= 0 ? g.insnap.p + (int64_t)snap * (m - top0) : g.insnap.p, top0, owner_end, m,
+                           out.iptr.p);
+        HTRI_LAUNCH_CHECK();
     }
-    HTRI_HIP(hipStreamSynchronize(s));
+    scan_exclusive_i64(A, out.iptr.p, out.iptr.p, m, out.iptr.p + m, s);
+    if (read_i64(out.iptr.p + m, s) != n) fail(HTRI_E_DEVICE, "in-list counts do not add up to the hyperwedges");
+    if (n > 0) {
+        DBuf<unsigned int> bad(A, 1);
+        fill_u32(bad.p, 1, 0, s);
+        hipLaunchKernelGGL(k_inlist_fill, dim3(grid_for(owner_end * kWave, 256, 16384)), dim3(256), 0, s, g.fptr.p,
+                           g.fadj.p, g.wbits, owner_end, g.esize.p, g.eptr.p, g.emem.p, g.mptr.p, g.fmask.p,
+                           out.iptr.p, g.inpos.p, out.inl.p, bad.p);
+        HTRI_LAUNCH_CHECK();
+        unsigned int hb = 0;
+        HTRI_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(hb), hipMemcpyDeviceToHost, s));
+        HTRI_HIP(hipStreamSynchronize(s));
+        if (hb) fail(HTRI_E_DEVICE, "in-list slot outside its middle's range");
+    }
+}
+
+void build_items_mid(Graph &g, int32_t gid, const CloseConfig &cfg, const InList &in, ItemLists &out) {
+    hipStream_t s = g.stream;
+    const int64_t m = g.m;
+    DBuf<int64_t> icnt(g.al, m + 1), wcnt(g.al, m + 1);
+    if (m > 0) {
+        hipLaunchKernelGGL(k_item_counts_mid, dim3(grid_for(m, 256)), dim3(256), 0, s, g.fptr.p, in.iptr.p, in.inl.p,
+                           g.wbits, m, cfg.cap, cfg.jp, icnt.p, wcnt.p);
+        HTRI_LAUNCH_CHECK();
+    }
+    items_from_counts(g, icnt, wcnt, out, [&] {
+        hipLaunchKernelGGL(k_item_fill_mid, dim3(grid_for(m, 256)), dim3(256), 0, s, g.fptr.p, in.iptr.p, m, cfg.cap,
+                           cfg.jp, gid, icnt.p, wcnt.p, out.block.p, out.wave.p);
+        HTRI_LAUNCH_CHECK();
+    });
 }
 
 // ---------------------------------------------------------------- dense window
@@ -1056,7 +1425,7 @@ namespace {
 // private vertex), i.e. |K_v & BF1_j|.  The owner's kWinClasses largest
 // classes are counted this way; the other hits are enumerated bit by bit and
 // classified by their regions like probed hits.
-constexpr int kWinRowsMax = 131072;
+constexpr int kWinRowsMax = (int)kWindowRowsMax;
 constexpr int kWinWordsMax = kWinRowsMax / 32;
 constexpr int kWinClasses = 8;              // bulk-counted classes at most (fewer for wide windows)
 constexpr int kWinLdsBudget = 60 * 1024;    // bytes of row bitmaps per block of k_close_window
@@ -1342,10 +1711,12 @@ WindowPlan choose_window(Graph &g, uint32_t flags) {
     };
     const int64_t e_end = fptr_at(g.m);
     // candidates: the whole graph (or the largest window), then every power of
-    // two below it down to 1024 rows
+    // two below it down to 1024 rows (the starts window_start() lists)
     std::vector<int64_t> cands{std::min<int64_t>(g.m, kWinRowsMax)};
-    for (int64_t c = kWinRowsMax; c >= 1024; c /= 2)
+    for (int s = 0; s < kWindowStarts; s++) {
+        const int64_t c = kWindowRowsMax >> s;
         if (c < cands[0]) cands.push_back(c);
+    }
     for (const int64_t n : cands) {
         const int64_t w0 = g.m - n;
         const int64_t inside = e_end - fptr_at(w0);
@@ -1711,6 +2082,26 @@ const uint8_t *pattern_lut() {
 
 // ---------------------------------------------------------------- driver
 
+// S and S outside the window of the last count (cstats[0] and [7]), out of
+// the count's own time
+void closure_stream_stats(Graph &g) {
+    if (g.cstats[0] >= 0 || !g.have_wedges) return;
+    hipStream_t s = g.stream;
+    DBuf<unsigned long long> S(g.al, 2);
+    fill_u64((uint64_t *)S.p, 2, 0, s);
+    if (g.nw > 0) {
+        const int64_t e_split = g.stats_owner_end < g.m ? read_i64(g.fptr.p + g.stats_owner_end, s) : g.nw;
+        hipLaunchKernelGGL(k_stream_size, dim3(grid_for(g.nw, 256, 2048)), dim3(256), 0, s, g.fptr.p, g.fadj.p, g.nw,
+                           e_split, g.wbits, S.p);
+        HTRI_LAUNCH_CHECK();
+    }
+    unsigned long long h[2] = {0, 0};
+    HTRI_HIP(hipMemcpyAsync(h, S.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    HTRI_HIP(hipStreamSynchronize(s));
+    g.cstats[0] = (int64_t)h[0];
+    g.cstats[7] = (int64_t)h[1];
+}
+
 void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21], uint64_t *t_dev, uint32_t *cw_dev) {
     hipStream_t s = g.stream;
     Allocator &A = g.al;
@@ -1726,18 +2117,47 @@ void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21],
 
     const WindowPlan win = choose_window(g, flags);
     const int64_t owner_end = win.nrows ? win.w0 : m;
+    // probing direction: around the middle hyperedge unless asked otherwise
+    // or its in-list does not fit (then around the owner)
+    bool mid = !(flags & HTRI_COUNT_OWNER_PROBE) && owner_end > 0;
+    if (mid) {
+        size_t free_b = 0, total_b = 0;
+        const int64_t n_in = read_i64(g.fptr.p + owner_end, s);
+        if (n_in >= (int64_t)UINT32_MAX) mid = false;
+        else if (hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+                 (double)inlist_bytes(g, owner_end) > 0.9 * (double)free_b)
+            mid = false;
+    }
+    InList in;
     ItemLists items;
-    build_items(g, 0, cfg, items, owner_end);
+    if (mid) {
+        try {
+            build_inlist(g, owner_end, in);
+            build_items_mid(g, 0, cfg, in, items);
+        } catch (const Error &e) {
+            if (e.code != HTRI_E_OOM) throw;
+            HTRI_HIP(hipStreamSynchronize(s));
+            in = InList();
+            items = ItemLists();
+            mid = false;
+        }
+    }
+    if (!mid) build_items(g, 0, cfg, items, owner_end);
     const int64_t nitems = items.nblock + items.nwave;
     DBuf<uint8_t> lut(A, 128);
     HTRI_HIP(hipMemcpyAsync(lut.p, pattern_lut(), 128, hipMemcpyHostToDevice, s));
     DBuf<GraphDesc> desc(A, 1);
     GraphDesc hd = graph_desc(g);
+    if (mid) {
+        hd.inl = in.inl.p;
+        hd.iptr = in.iptr.p;
+    }
     HTRI_HIP(hipMemcpyAsync(desc.p, &hd, sizeof(GraphDesc), hipMemcpyHostToDevice, s));
     // counters: [0] block queue, [1..21] pattern counts, [22] probes,
-    // [23] wave queue, [24] S, [25] S before the window, [26..27] window stats
-    DBuf<unsigned long long> ctr(A, 28);
-    fill_u64((uint64_t *)ctr.p, 28, 0, s);
+    // [23] wave queue, [24] S, [25] S before the window, [26..27] window
+    // stats, [28] hashed entries staged
+    DBuf<unsigned long long> ctr(A, 29);
+    fill_u64((uint64_t *)ctr.p, 29, 0, s);
 
     const bool pe = t_dev != nullptr;
     const bool pw = cw_dev != nullptr;
@@ -1750,7 +2170,7 @@ void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21],
     }
     if (pw) fill_u32(cw_dev, g.nw, 0, s);
 
-    int nblocks = device_cu_count() * close_blocks_per_cu(cfg, pe, pw);
+    int nblocks = device_cu_count() * close_blocks_per_cu(cfg, pe, pw, mid);
     if ((int64_t)nblocks > nitems) nblocks = (int)std::max<int64_t>(nitems, 1);
     HTRI_HIP(hipStreamSynchronize(s));
     HTRI_HIP(hipEventRecord(e1, s));
@@ -1770,21 +2190,13 @@ void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21],
     a.cwkm = cwkm.p;
     a.counts = ctr.p + 1;
     a.probes = ctr.p + 22;
+    a.staged = ctr.p + 28;
+    a.kdirect_end = owner_end;
     close_window(g, win, mask, lut.p, ctr.p + 1, ctr.p + 26, cw_dev, pe ? cwjm.p : nullptr, pe ? cwkm.p : nullptr);
     HTRI_HIP(hipEventRecord(ew, s));
-    launch_close_kernel(cfg, pe, pw, a, nblocks, s);
+    launch_close_kernel(cfg, pe, pw, a, nblocks, s, mid);
     HTRI_HIP(hipEventRecord(e2, s));
 
-    if (g.nw > 0) {
-        int64_t e_split = g.nw;
-        if (win.nrows) {
-            HTRI_HIP(hipMemcpyAsync(&e_split, g.fptr.p + win.w0, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-            HTRI_HIP(hipStreamSynchronize(s));
-        }
-        hipLaunchKernelGGL(k_stream_size, dim3(grid_for(g.nw, 256, 2048)), dim3(256), 0, s, g.fptr.p, g.fadj.p, g.nw,
-                           e_split, g.wbits, ctr.p + 24);
-        HTRI_LAUNCH_CHECK();
-    }
     if (pe) {
         DBuf<unsigned long long> t(A, m);
         fill_u64((uint64_t *)t.p, m, 0, s);
@@ -1806,7 +2218,7 @@ void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21],
     } else {
         HTRI_HIP(hipEventRecord(e3, s));
     }
-    unsigned long long hc[28];
+    unsigned long long hc[29];
     HTRI_HIP(hipMemcpyAsync(hc, ctr.p, sizeof(hc), hipMemcpyDeviceToHost, s));
     HTRI_HIP(hipStreamSynchronize(s));
     int64_t tot = 0;
@@ -1824,18 +2236,23 @@ void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21],
     }
     HTRI_HIP(hipStreamSynchronize(s));
     if (!win.nrows) mask_words_before = mask_words_total;
-    g.cstats[0] = (int64_t)hc[24];
+    g.cstats[0] = -1;                 // S: computed on request (closure_stream_stats)
     g.cstats[1] = (int64_t)hc[22];
     g.cstats[2] = nitems;
     g.cstats[3] = mask_words_total;
     g.cstats[4] = nblocks;
     g.cstats[5] = win.nrows;
     g.cstats[6] = win.wedges;
-    g.cstats[7] = (int64_t)hc[25];
+    g.cstats[7] = -1;
+    g.stats_owner_end = owner_end;
     g.cstats[8] = wedges_before;
     g.cstats[9] = mask_words_before;
     g.cstats[10] = (int64_t)hc[26];
     g.cstats[11] = (int64_t)hc[27];
+    g.cstats[12] = mid ? 1 : 0;
+    g.cstats[13] = mid ? in.n : 0;
+    g.cstats[14] = 0;
+    g.cstats[15] = (int64_t)hc[28];
     HTRI_HIP(hipEventElapsedTime(&g.tm.schedule_ms, e0, e1));
     HTRI_HIP(hipEventElapsedTime(&g.tm.closure_ms, e1, e2));
     HTRI_HIP(hipEventElapsedTime(&g.tm.window_ms, e1, ew));

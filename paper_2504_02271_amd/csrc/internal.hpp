@@ -165,11 +165,28 @@ struct Graph {
     DBuf<int64_t> mptr;         // m+1, offsets (in 32-bit words) of Omega masks
     DBuf<uint32_t> fmask;
     DBuf<uint32_t> indeg;       // earlier neighbours of each hyperedge
+    // slot of each hyperwedge (r, j) among j's earlier neighbours: the owners
+    // are counted in rank ranges split at the dense window's possible starts,
+    // so the owners before any such start hold j's first slots
+    DBuf<uint32_t> inpos;
+    DBuf<uint32_t> insnap;      // kWindowStarts snapshots of indeg over ranks [insnap_top, m)
+    int64_t insnap_top = 0;
     int64_t summary[6] = {0, 0, 0, 0, 0, 0};
 
     Timings tm;
-    int64_t cstats[12] = {0};
+    int64_t cstats[16] = {0};
+    int64_t stats_owner_end = 0;   // window start of the last count (for the S census)
 };
+
+// The dense window's possible starts: m minus a power of two of rows from
+// kWindowRowsMax down to kWindowRowsMax >> (kWindowStarts - 1), or 0 (the
+// whole graph).
+constexpr int64_t kWindowRowsMax = 131072;
+constexpr int kWindowStarts = 8;
+inline int64_t window_start(int64_t m, int s) {
+    const int64_t w = m - (kWindowRowsMax >> s);
+    return w > 0 ? w : 0;
+}
 
 // api.hip: message for htri_last_error(NULL)
 void set_load_error(const std::string &msg);
@@ -189,11 +206,16 @@ struct GraphDesc {
     const int32_t *esize;
     const int64_t *eptr;
     const int32_t *emem;
+    // middle-centric closure only (null otherwise): the in-list of each
+    // middle hyperedge j, i.e. the hyperwedges (r, j) of the owners probed
+    const uint4 *inl;           // per entry: InEntry below
+    const int64_t *iptr;        // m+1: in-list of j at [iptr[j], iptr[j+1])
     int32_t wbits;
     int32_t pad;
 };
 // A closure work item: graph g, owner r, chunk [cb, ce) of N+(r), partner
-// positions [jb, je) of N+(r).
+// positions [jb, je) of N+(r).  Middle-centric items: r is the middle j,
+// [cb, ce) a chunk of N+(j) and [jb, je) positions in j's in-list.
 struct Item {
     int32_t g, r, cb, ce, jb, je;
 };
@@ -217,6 +239,9 @@ struct CloseArgs {
     uint32_t *cwkm;                 // per-wedge k-role count, masked
     unsigned long long *counts;     // [graphs][21]; [g][0] unused (total formed on the host)
     unsigned long long *probes;     // entries probed
+    unsigned long long *staged;     // hashed entries staged (null: not counted)
+    int64_t kdirect_end;            // middle-centric: middles >= this add k-role counts atomically
+                                    // (the dense window has written those hyperwedges' counters)
 };
 // Owners with at most kWaveOwnerMax forward entries whose partner lists hold
 // at most kWaveStreamMax entries in total are closed by one wave each.
@@ -227,6 +252,25 @@ struct ItemLists {
     int64_t nblock = 0, nwave = 0;
 };
 GraphDesc graph_desc(const Graph &g);
+// The in-list of the middle-centric closure: every hyperwedge (r, j) with
+// r < owner_end, grouped by j (the transpose of the forward adjacency's
+// prefix; no order inside a group).
+// One entry, 16 bytes, for the hyperwedge (r, j) at forward index i:
+//   x = i; y = (len << wbits) | omega_rj with len = |N+(r)| - 1 - (position
+//   of j in N+(r)), the entries after j; z = the one shared vertex when
+//   omega_rj = 1 and e_r has a stored mask, else kInNoVertex; w = (r << wbits)
+//   | |e_r|.  Both packings fit as the forward entries do.
+constexpr uint32_t kInNoVertex = 0xFFFFFFFFu;
+struct InList {
+    DBuf<uint4> inl;
+    DBuf<int64_t> iptr;
+    int64_t n = 0;
+};
+// device bytes build_inlist needs at its peak
+int64_t inlist_bytes(Graph &g, int64_t owner_end);
+void build_inlist(Graph &g, int64_t owner_end, InList &out);
+// middle-centric work items of one graph
+void build_items_mid(Graph &g, int32_t gid, const CloseConfig &cfg, const InList &in, ItemLists &out);
 // work items of one graph (graph index gid) for a configuration; owners at
 // ranks >= owner_end get none (the dense window closes them)
 void build_items(Graph &g, int32_t gid, const CloseConfig &cfg, ItemLists &out, int64_t owner_end);
@@ -239,8 +283,10 @@ struct WindowPlan {
 WindowPlan choose_window(Graph &g, uint32_t flags);
 void close_window(Graph &g, const WindowPlan &w, uint32_t emask, const uint8_t *lut_dev, unsigned long long *counts,
                   unsigned long long *stats, uint32_t *cwj, uint32_t *cwjm, uint32_t *cwkm);
-int close_blocks_per_cu(const CloseConfig &cfg, bool pe, bool pw);
-void launch_close_kernel(const CloseConfig &cfg, bool pe, bool pw, const CloseArgs &a, int nblocks, hipStream_t s);
+// mid: middle-centric items (default configuration only)
+int close_blocks_per_cu(const CloseConfig &cfg, bool pe, bool pw, bool mid = false);
+void launch_close_kernel(const CloseConfig &cfg, bool pe, bool pw, const CloseArgs &a, int nblocks, hipStream_t s,
+                         bool mid = false);
 bool valid_config(const CloseConfig &cfg);
 // patterns 1-8 only, by searching around the inclusion hyperwedges; with
 // dev_out, also the triangles of pattern target (sorted normalised triples)
@@ -251,6 +297,8 @@ void count_inclusion_classes(Graph &g, uint32_t mask, int64_t counts[21], uint64
 void enumerate_all_wedges(Graph &g, int target, int64_t capacity, int32_t *dev_out, unsigned long long *dev_found);
 void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21], uint64_t *t_dev /*m or null*/,
                     uint32_t *cw_dev /*nw or null*/);
+// fill the S entries of the last count's census (run on request)
+void closure_stream_stats(Graph &g);
 // sample.hip: closure of explicit wedges (per-sample counts) and weighted
 // sums over uniform (mode 1) or pool (mode 2) draws
 void close_wedge_list_counts(Graph &g, const int64_t *dev_idx, int64_t n, int64_t *dev_out);

@@ -23,6 +23,7 @@ HTRI_ORDER_INPUT = 8
 HTRI_COUNT_NO_WINDOW = 16
 HTRI_COUNT_WINDOW_ALWAYS = 32
 HTRI_COUNT_INCLUSION_CLASSES = 64
+HTRI_COUNT_OWNER_PROBE = 128
 HTRI_SAMPLE_EXACT_INCLUSION = 1
 _WINDOW_FLAGS = {"auto": 0, "off": HTRI_COUNT_NO_WINDOW, "always": HTRI_COUNT_WINDOW_ALWAYS,
                  "inclusion_classes": HTRI_COUNT_INCLUSION_CLASSES}
@@ -259,15 +260,20 @@ class Graph:
         return src, dst, om
 
     def count_patterns(self, mask: int = 0, per_edge: bool = False, per_wedge: bool = False,
-                       device_out: bool = False, window: str = "auto"):
+                       device_out: bool = False, window: str = "auto", probe: str = "middle"):
         """Returns (counts int64[21], per_edge or None, per_wedge or None).
         With device_out the per-edge/per-wedge results are torch tensors on the GPU.
         window: "auto" (dense top-rank window when it pays), "off", "always", or
         "inclusion_classes" (patterns 1-8 only, searched around the inclusion
-        hyperwedges; no per_wedge)."""
+        hyperwedges; no per_wedge).
+        probe: "middle" (each hyperwedge (r, j) probes the rest of N+(r)
+        against N+(j); the library falls back to "owner" when its lists do
+        not fit) or "owner" (each partner's N+(j) against N+(r))."""
         counts = np.zeros(21, np.int64)
         pe = pw = None
-        flags = _WINDOW_FLAGS[window]
+        if probe not in ("middle", "owner"):
+            raise ValueError(f"probe must be 'middle' or 'owner', not {probe!r}")
+        flags = _WINDOW_FLAGS[window] | (HTRI_COUNT_OWNER_PROBE if probe == "owner" else 0)
         if device_out:
             import torch
             flags |= HTRI_OUTPUT_ON_DEVICE
@@ -304,8 +310,10 @@ class Graph:
     def closure_stats(self) -> np.ndarray:
         """[S, probed entries, work items, Omega mask words, closure blocks,
         window rows, window wedges, S outside the window, wedges outside,
-        mask words outside, window bitmap words read, window hits enumerated]"""
-        out = np.zeros(12, np.int64)
+        mask words outside, window bitmap words read, window hits enumerated,
+        middle-centric probing (1/0), in-list hyperwedges, in-list mask
+        words, hashed entries staged]"""
+        out = np.zeros(16, np.int64)
         _check(self._lib.htri_closure_stats(self._h, _ptr(out)), "htri_closure_stats", self._h)
         return out
 

@@ -66,17 +66,24 @@ def check_exact(htri, g, flags=None, wedge_sample=None, nthreads=0, seed=0, wind
         idx = np.sort(rng.choice(idx.shape[0], size=wedge_sample, replace=False))
     want = o.wedge_closure_ranked(rank, src[idx], dst[idx])[:, 0]
     for win in windows:
-        counts, pe, pw = G.count_patterns(per_edge=True, per_wedge=True, window=win)
-        st = G.closure_stats()
-        print(f"[check_exact]   window={win}: rows {st[5]}, wedges inside {st[6]}, enumerated {st[11]}", flush=True)
-        if win == "always" and G.num_wedges > 0 and 3 <= G.num_edges <= 16384:
-            assert st[5] == G.num_edges
-        if win == "off":
-            assert st[5] == 0
-        assert np.array_equal(counts, r.H), (win, counts, r.H)
-        assert np.array_equal(pe, r.t), win
-        assert int(pw.astype(np.int64).sum()) == int(counts[0])
-        assert np.array_equal(pw[idx].astype(np.int64), want), win
+        for probe in ("middle", "owner"):
+            counts, pe, pw = G.count_patterns(per_edge=True, per_wedge=True, window=win, probe=probe)
+            st = G.closure_stats()
+            print(f"[check_exact]   window={win} probe={probe}: rows {st[5]}, wedges inside {st[6]}, "
+                  f"enumerated {st[11]}, middle-centric {st[12]}, in-list {st[13]}", flush=True)
+            if win == "always" and G.num_wedges > 0 and 3 <= G.num_edges <= 16384:
+                assert st[5] == G.num_edges
+            if win == "off":
+                assert st[5] == 0
+            if probe == "owner" or st[5] == G.num_edges:
+                assert st[12] == 0 and st[13] == 0
+            else:
+                # every hyperwedge outside the window is in the in-list
+                assert st[12] == 1 and st[13] == st[8], (st[12], st[13], st[8])
+            assert np.array_equal(counts, r.H), (win, probe, counts, r.H)
+            assert np.array_equal(pe, r.t), (win, probe)
+            assert int(pw.astype(np.int64).sum()) == int(counts[0])
+            assert np.array_equal(pw[idx].astype(np.int64), want), (win, probe)
     # classes with an inclusion hyperwedge only (patterns 1-8), searched around those hyperwedges
     incl_mask = 0x1FE
     ci, pei, _ = G.count_patterns(mask=incl_mask, per_edge=True, window="inclusion_classes")

@@ -45,6 +45,22 @@ def test_window_and_probing_agree(full):
     print(f"\n[fullsize] window rows {st[5]}: probing alone agrees", flush=True)
 
 
+def test_probing_directions_agree(full):
+    """Middle-centric probing (the default) and owner-centric probing give the
+    same counts, per-hyperedge counts and per-wedge closures at full size,
+    with and without the dense window."""
+    G = full["G"]
+    assert G.closure_stats()[12] == 1
+    for win in ("auto", "off"):
+        c1, pe1, pw1 = G.count_patterns(per_edge=True, per_wedge=True, window=win, probe="owner")
+        st = G.closure_stats()
+        assert st[12] == 0
+        assert np.array_equal(c1, full["counts"]), win
+        assert np.array_equal(pe1, full["pe"]), win
+        assert np.array_equal(pw1, full["pw"]), win
+        print(f"\n[fullsize] window={win}: owner-centric probing agrees", flush=True)
+
+
 def test_invariants(full):
     counts, pe, pw, s = full["counts"], full["pe"], full["pw"], full["s"]
     assert counts[1:].sum() == counts[0] > 0
