@@ -44,10 +44,17 @@ def log(*a):
 
 def closure_bytes(cstats):
     """Algorithmic bytes of one launch of the probing closure kernel (the
-    owners outside the dense window): the probe stream (4 B packed entry per
-    partner-list entry, S of them), the owner lists staged once (4 B entry +
-    4 B size of the third hyperedge per hyperwedge, plus the Omega mask
-    words), and the two 4 B per-wedge role counters written."""
+    owners outside the dense window).
+    Middle-centric (the default): the probe stream (4 B packed entry per
+    probed entry of N+(r) after j), the in-list (one 16 B entry per
+    hyperwedge, and its 4 B j-role counter written), and the hashed lists of
+    the middles staged in LDS (4 B entry, 4 B size of the third hyperedge, 4 B
+    first Omega word, and the 4 B k-role counter written, per entry).
+    Owner-centric: the probe stream (S entries of the partners' lists), the
+    owner lists staged once (entry + size + Omega words) and the two role
+    counters."""
+    if int(cstats[12]) == 1:
+        return 4 * int(cstats[1]) + 20 * int(cstats[13]) + 16 * int(cstats[15])
     S_probe = int(cstats[7])
     nw_probe = int(cstats[8])
     mask_words = int(cstats[9])
@@ -343,15 +350,18 @@ def main() -> int:
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_close (probing closure + classify + per-block reduce, owners outside the dense window)",
+            "kernel": "k_close (probing closure + classify + per-block reduce, owners outside the dense window; "
+                      + ("middle-centric" if int(cstats[12]) == 1 else "owner-centric") + " probing)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "algorithmic_bytes": B,
-            "probe_stream_S": int(cstats[7]),
+            "probe_stream_S_owner_centric": int(cstats[7]),
             "entries_probed": int(cstats[1]),
+            "in_list_hyperwedges": int(cstats[13]),
+            "hashed_entries_staged": int(cstats[15]),
         },
         "window": {
             "kernels": "k_window_rows + k_close_window (owners of the top ranks, bitmap intersection)",

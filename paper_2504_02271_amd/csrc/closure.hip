@@ -183,6 +183,10 @@ __device__ __forceinline__ void flush_wave_counts(unsigned long long &wcnt, unsi
 }
 
 constexpr int kUnroll = 4;   // partner-list entries per lane per step
+// Items a block or a wave claims from its queue with one atomic (one hot
+// address: fewer round trips, and the claimed items run back to back).
+constexpr unsigned int kBlockBatch = 4;
+constexpr unsigned int kWaveBatch = 8;
 
 // What a probe needs of the partner j: |e_j|, omega_rj, Omega_rj (mask
 // words over the owner's members), whether the common-vertex shortcut can
@@ -420,16 +424,18 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
     unsigned long long all_probes = 0, all_staged = 0;
     int cur_g = -1;
 
+    int64_t bnext = 0, bend = 0;     // claimed queue positions [bnext, bend), block-uniform
     for (;;) {
         __syncthreads();
-        if (tid == 0) {
-            unsigned int c = atomicAdd(A.queue, 1u);
-            sh_item = (int64_t)c < A.nitems ? A.nitems - 1 - (int64_t)c : -1;
+        if (bnext >= bend) {
+            if (tid == 0) sh_item = (int64_t)atomicAdd(A.queue, kBlockBatch);
+            __syncthreads();
+            bnext = sh_item;
+            bend = bnext + kBlockBatch;
         }
-        __syncthreads();
-        const int64_t it = sh_item;
-        if (it < 0) break;
-        const Item item = A.items[it];
+        const int64_t c = bnext++;
+        if (c >= A.nitems) break;
+        const Item item = A.items[A.nitems - 1 - c];
         if (item.g != cur_g) {
             if (cur_g >= 0) flush_wave_counts(wcnt, c9, A.counts, cur_g, lane);
             cur_g = item.g;
@@ -823,12 +829,17 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
     const uint32_t *p_ent = MID ? Wl.p_ent : Wl.ent;
     const uint32_t *p_mx = MID ? Wl.p_mx : Wl.ent_mx;
     unsigned long long wprobes = 0, wstaged = 0;
+    int64_t wnext = 0, wend = 0;     // claimed queue positions [wnext, wend)
     for (;;) {
-        unsigned int c = 0;
-        if (lane == 0) c = atomicAdd(A.wqueue, 1u);
-        c = (unsigned int)__builtin_amdgcn_readfirstlane((int)c);
-        if ((int64_t)c >= A.nwitems) break;
-        const Item item = A.witems[A.nwitems - 1 - (int64_t)c];
+        if (wnext >= wend) {
+            unsigned int c0 = 0;
+            if (lane == 0) c0 = atomicAdd(A.wqueue, kWaveBatch);
+            wnext = (unsigned int)__builtin_amdgcn_readfirstlane((int)c0);
+            wend = wnext + kWaveBatch;
+        }
+        const int64_t c = wnext++;
+        if (c >= A.nwitems) break;
+        const Item item = A.witems[A.nwitems - 1 - c];
         if (item.g != cur_g) {
             if (cur_g >= 0) flush_wave_counts(wcnt, c9, A.counts, cur_g, lane);
             cur_g = item.g;
@@ -1318,7 +1329,7 @@ void items_from_counts(Graph &g, DBuf<int64_t> &icnt, DBuf<int64_t> &wcnt, ItemL
     HTRI_HIP(hipStreamSynchronize(s));
     out.nblock = tot[0];
     out.nwave = tot[1];
-    // the item counters are 32-bit and run past the end by one per block or wave
+    // the item counters are 32-bit and run past the end by one claim per block or wave
     const int64_t limit = (int64_t)UINT32_MAX - ((int64_t)1 << 24);
     if (out.nblock >= limit || out.nwave >= limit) fail(HTRI_E_UNSUPPORTED, "too many work items");
     out.block.alloc(A, out.nblock);
