@@ -182,7 +182,6 @@ __device__ __forceinline__ void flush_wave_counts(unsigned long long &wcnt, unsi
     c9 = 0;
 }
 
-constexpr int kUnroll = 4;   // partner-list entries per lane per step
 // Items a block or a wave claims from its queue with one atomic (one hot
 // address: fewer round trips, and the claimed items run back to back).
 constexpr unsigned int kBlockBatch = 4;
@@ -199,7 +198,7 @@ struct JParams {
     int32_t jr;
 };
 
-// kUnroll partner-list entries e[u] = (k, omega_jk) per lane (partner data
+// U partner-list entries e[u] = (k, omega_jk) per lane (partner data
 // for the shortcut test in fwij / fm0 / ffast, the rest from jparams) against the
 // chunk of owner r staged in the bucketed open-addressing table (two
 // (entry, position) slots per 16-byte bucket, buckets probed linearly; a
@@ -212,29 +211,29 @@ struct JParams {
 // other hits.  hit[u]: entry u closes a hyper-triangle; mhit[u]: it counts
 // towards the per-hyperedge counts; po[u]: its pattern unless it is the
 // common-vertex one (counted in c9), else 0.
-template <bool PER_EDGE, typename JF>
+template <int U, bool PER_EDGE, typename JF>
 __device__ __forceinline__ void probe_tile(const uint2 *tab, int hbits, int wbits, uint32_t wmask,
-                                           const uint32_t (&e)[kUnroll], const bool (&val)[kUnroll],
-                                           const int (&fwij)[kUnroll], const uint32_t (&fm0)[kUnroll],
-                                           const bool (&ffast)[kUnroll],
+                                           const uint32_t (&e)[U], const bool (&val)[U],
+                                           const int (&fwij)[U], const uint32_t (&fm0)[U],
+                                           const bool (&ffast)[U],
                                            const JF &jparams, const uint2 *ent_sm, const uint32_t *ent_mx,
                                            uint32_t *ent_ck, const uint8_t *lut, int W, int si, const GraphDesc &G,
                                            int32_t r, uint32_t emask, unsigned long long &c9,
-                                           bool (&hit)[kUnroll], bool (&mhit)[kUnroll], uint32_t (&po)[kUnroll]) {
+                                           bool (&hit)[U], bool (&mhit)[U], uint32_t (&po)[U]) {
     const uint4 *tq = reinterpret_cast<const uint4 *>(tab);
     const uint32_t nbm1 = (1u << (hbits - 1)) - 1;
     const uint32_t kmask = ~wmask;
-    uint32_t b[kUnroll];
-    uint4 B[kUnroll];
+    uint32_t b[U];
+    uint4 B[U];
 #pragma unroll
-    for (int u = 0; u < kUnroll; u++) b[u] = hslot(e[u] >> wbits, hbits - 1);
+    for (int u = 0; u < U; u++) b[u] = hslot(e[u] >> wbits, hbits - 1);
 #pragma unroll
-    for (int u = 0; u < kUnroll; u++) B[u] = tq[b[u]];
-    uint2 sl[kUnroll];
-    bool cont[kUnroll];
+    for (int u = 0; u < U; u++) B[u] = tq[b[u]];
+    uint2 sl[U];
+    bool cont[U];
     bool more = false;
 #pragma unroll
-    for (int u = 0; u < kUnroll; u++) {
+    for (int u = 0; u < U; u++) {
         // an empty slot's entry word is 0 and a probed key k << wbits never is (k > j > r >= 0)
         const uint32_t kk = e[u] & kmask;
         const bool h0 = (B[u].x & kmask) == kk;
@@ -246,7 +245,7 @@ __device__ __forceinline__ void probe_tile(const uint2 *tab, int hbits, int wbit
     }
     if (more) {
 #pragma unroll
-        for (int u = 0; u < kUnroll; u++) {
+        for (int u = 0; u < U; u++) {
             if (cont[u]) {
                 const uint32_t kk = e[u] & kmask;
                 uint32_t bb = b[u];
@@ -263,14 +262,14 @@ __device__ __forceinline__ void probe_tile(const uint2 *tab, int hbits, int wbit
             }
         }
     }
-    uint2 sm[kUnroll];
+    uint2 sm[U];
 #pragma unroll
-    for (int u = 0; u < kUnroll; u++) sm[u] = ent_sm[hit[u] ? sl[u].y : 0u];
-    bool fast[kUnroll];
+    for (int u = 0; u < U; u++) sm[u] = ent_sm[hit[u] ? sl[u].y : 0u];
+    bool fast[U];
     bool slow = false;
     uint32_t n9 = 0;
 #pragma unroll
-    for (int u = 0; u < kUnroll; u++) {
+    for (int u = 0; u < U; u++) {
         const int wik = (int)(sl[u].x & wmask), wjk = (int)(e[u] & wmask);
         fast[u] = hit[u] & ffast[u] & (wik == fwij[u]) & (wjk == fwij[u]) & (sm[u].y == fm0[u]) &
                   ((int)sm[u].x > fwij[u]);
@@ -280,7 +279,7 @@ __device__ __forceinline__ void probe_tile(const uint2 *tab, int hbits, int wbit
     }
     if (slow) {
 #pragma unroll
-        for (int u = 0; u < kUnroll; u++) {
+        for (int u = 0; u < U; u++) {
             if (hit[u] && !fast[u]) {
                 const JParams J = jparams(u);
                 const uint32_t pos = sl[u].y;
@@ -308,21 +307,22 @@ __device__ __forceinline__ void probe_tile(const uint2 *tab, int hbits, int wbit
         // every pattern counted per hyperedge (the default): a hit is a counted hit
         const bool all_patterns = (emask & 0x1FFFFEu) == 0x1FFFFEu;
 #pragma unroll
-        for (int u = 0; u < kUnroll; u++) {
+        for (int u = 0; u < U; u++) {
             const uint32_t p = po[u] ? po[u] : kPatternCommonVertex;
             mhit[u] = hit[u] && (all_patterns || ((emask >> p) & 1u));
             if (mhit[u]) atomicAdd(&ent_ck[sl[u].y], 1u);
         }
     } else {
 #pragma unroll
-        for (int u = 0; u < kUnroll; u++) mhit[u] = false;
+        for (int u = 0; u < U; u++) mhit[u] = false;
     }
 }
 
 // Add the wave's other-pattern hits (po[u] != 0) into lane p's counter.
+template <int U>
 __device__ __forceinline__ void aggregate_other(const uint32_t *po, int lane, unsigned long long &wcnt) {
 #pragma unroll
-    for (int u = 0; u < kUnroll; u++) {
+    for (int u = 0; u < U; u++) {
         uint64_t pend = __ballot(po[u] != 0);
         while (pend) {
             const int srcl = __ffsll((unsigned long long)pend) - 1;
@@ -395,6 +395,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 template <int CAP, int JP, bool PER_EDGE, bool PER_WEDGE, bool MID>
 __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
     static_assert(JP <= kBlock, "one thread per partner");
+    // partner-list entries per lane per step: fewer registers for the short
+    // middle-centric segments, more loads in flight for the long partner lists
+    constexpr int kU = MID ? 2 : 4;
     constexpr int HMAX = 4 * CAP;
     static_assert(sizeof(CloseWaveLds<MID>) % 16 == 0, "wave slices keep the table 16-byte aligned");
     __shared__ __align__(16) CloseLds<CAP, JP, PER_EDGE, PER_WEDGE, MID> L;
@@ -578,17 +581,17 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
         if (total >= (int64_t)nseg * 256) {
             // Dense items (long partner segments): one wave per partner, the
             // partner's data wave-uniform, lanes striding over its segment.
-            constexpr int TILE = kWave * kUnroll;
+            constexpr int TILE = kWave * kU;
             int qd = wave;
             while (qd < nseg && seg_pre[qd + 1] == seg_pre[qd]) qd += kBlock / kWave;
             int64_t i0 = 0;
-            uint32_t entA[kUnroll];
-            bool valA[kUnroll];
+            uint32_t entA[kU];
+            bool valA[kU];
             if (qd < nseg) {
                 const int64_t slen = seg_pre[qd + 1] - seg_pre[qd];
                 const int64_t sbase = seg_src[qd];
 #pragma unroll
-                for (int u = 0; u < kUnroll; u++) {
+                for (int u = 0; u < kU; u++) {
                     const int64_t i = u * kWave + lane;
                     valA[u] = i < slen;
                     entA[u] = valA[u] ? gld(G.fadj + sbase + i) : 0u;
@@ -605,20 +608,20 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                     while (qn < nseg && seg_pre[qn + 1] == seg_pre[qn]) qn += kBlock / kWave;
                     in = 0;
                 }
-                uint32_t entB[kUnroll];
-                bool valB[kUnroll];
+                uint32_t entB[kU];
+                bool valB[kU];
                 if (qn < nseg) {
                     const int64_t nlen = seg_pre[qn + 1] - seg_pre[qn];
                     const int64_t nbase = seg_src[qn];
 #pragma unroll
-                    for (int u = 0; u < kUnroll; u++) {
+                    for (int u = 0; u < kU; u++) {
                         const int64_t i = in + u * kWave + lane;
                         valB[u] = i < nlen;
                         entB[u] = valB[u] ? gld(G.fadj + nbase + i) : 0u;
                     }
                 } else {
 #pragma unroll
-                    for (int u = 0; u < kUnroll; u++) {
+                    for (int u = 0; u < kU; u++) {
                         valB[u] = false;
                         entB[u] = 0u;
                     }
@@ -633,27 +636,27 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                 const bool fastd = (W == 1) && (si > wd) && (sjd > wd);
                 const int32_t jr = (W == 0) ? seg_rank(qd) : 0;
                 const JParams Jd{sjd, wd, fastd, m0, m1, m2, m3, jr};
-                bool hit[kUnroll], mhit[kUnroll];
-                uint32_t po[kUnroll];
-                int fwij[kUnroll];
-                uint32_t fm0[kUnroll];
-                bool ffast[kUnroll];
+                bool hit[kU], mhit[kU];
+                uint32_t po[kU];
+                int fwij[kU];
+                uint32_t fm0[kU];
+                bool ffast[kU];
 #pragma unroll
-                for (int u = 0; u < kUnroll; u++) {
+                for (int u = 0; u < kU; u++) {
                     fwij[u] = wd;
                     fm0[u] = m0;
                     ffast[u] = fastd;
                 }
-                probe_tile<PER_EDGE>(tab, hbits, wbits, wmask, entA, valA, fwij, fm0, ffast, [&](int) { return Jd; },
+                probe_tile<kU, PER_EDGE>(tab, hbits, wbits, wmask, entA, valA, fwij, fm0, ffast, [&](int) { return Jd; },
                                      ent_sm, ent_mx, ent_ck, lut, W, si, G, r, A.emask, c9, hit, mhit, po);
                 bool other = false;
 #pragma unroll
-                for (int u = 0; u < kUnroll; u++) {
+                for (int u = 0; u < kU; u++) {
                     other |= po[u] != 0;
                     if (PER_WEDGE) hits += (unsigned long long)__popcll(__ballot(hit[u]));
                     if (PER_EDGE) mhits += (unsigned long long)__popcll(__ballot(mhit[u]));
                 }
-                if (__ballot(other)) aggregate_other(po, lane, wcnt);
+                if (__ballot(other)) aggregate_other<kU>(po, lane, wcnt);
                 if (qn != qd) {
                     if (lane == 0) {
                         if (PER_WEDGE) seg_cj[qd] = (uint32_t)hits;
@@ -664,14 +667,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                 qd = qn;
                 i0 = in;
 #pragma unroll
-                for (int u = 0; u < kUnroll; u++) {
+                for (int u = 0; u < kU; u++) {
                     entA[u] = entB[u];
                     valA[u] = valB[u];
                 }
             }
         } else {
             // Flattened items: the partner segments laid end to end; each step
-            // a wave takes 64*kUnroll consecutive entries, kUnroll per lane.
+            // a wave takes 64*kU consecutive entries, kU per lane.
             // here total < nseg * 256 <= 65536: stream offsets fit in 32 bits
             const int total32 = (int)total;
             int qa = -1;                   // address cursor
@@ -679,10 +682,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
             int64_t srca = 0;
             int q = -1;                    // segment whose counters this lane holds
             uint32_t cj = 0, cjm = 0;
-            const int stride = kBlock * kUnroll;
+            const int stride = kBlock * kU;
             auto fetch = [&](int f0, uint32_t *ent, int *segu) {
 #pragma unroll
-                for (int u = 0; u < kUnroll; u++) {
+                for (int u = 0; u < kU; u++) {
                     const int f = f0 + u;
                     segu[u] = -1;
                     int64_t addr = 0;
@@ -703,37 +706,37 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                     ent[u] = segu[u] >= 0 ? gld(G.fadj + addr) : 0u;
                 }
             };
-            int fb = wave * kWave * kUnroll;
-            uint32_t entA[kUnroll];
-            int seguA[kUnroll];
-            if (fb < total32) fetch(fb + lane * kUnroll, entA, seguA);
+            int fb = wave * kWave * kU;
+            uint32_t entA[kU];
+            int seguA[kU];
+            if (fb < total32) fetch(fb + lane * kU, entA, seguA);
             for (; fb < total32; fb += stride) {
-                uint32_t entB[kUnroll];
-                int seguB[kUnroll];
+                uint32_t entB[kU];
+                int seguB[kU];
                 const int fbn = fb + stride;
                 if (fbn < total32) {
-                    fetch(fbn + lane * kUnroll, entB, seguB);
+                    fetch(fbn + lane * kU, entB, seguB);
                 } else {
 #pragma unroll
-                    for (int u = 0; u < kUnroll; u++) {
+                    for (int u = 0; u < kU; u++) {
                         entB[u] = 0u;
                         seguB[u] = -1;
                     }
                 }
-                bool valA[kUnroll], hit[kUnroll], mhit[kUnroll];
-                uint32_t po[kUnroll];
+                bool valA[kU], hit[kU], mhit[kU];
+                uint32_t po[kU];
 #pragma unroll
-                for (int u = 0; u < kUnroll; u++) valA[u] = seguA[u] >= 0;
+                for (int u = 0; u < kU; u++) valA[u] = seguA[u] >= 0;
                 // shortcut data per entry, reloaded only where the segment changes
-                int fwij[kUnroll];
-                uint32_t fm0[kUnroll];
-                bool ffast[kUnroll];
+                int fwij[kU];
+                uint32_t fm0[kU];
+                bool ffast[kU];
                 {
                     int qc = -1, cw = 0;
                     uint32_t cm = 0u;
                     bool cf = false;
 #pragma unroll
-                    for (int u = 0; u < kUnroll; u++) {
+                    for (int u = 0; u < kU; u++) {
                         const int qq = seguA[u] < 0 ? 0 : seguA[u];
                         if (qq != qc) {
                             qc = qq;
@@ -760,11 +763,11 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                     J.jr = (W == 0) ? seg_rank(qq) : 0;
                     return J;
                 };
-                probe_tile<PER_EDGE>(tab, hbits, wbits, wmask, entA, valA, fwij, fm0, ffast, jf, ent_sm, ent_mx, ent_ck,
+                probe_tile<kU, PER_EDGE>(tab, hbits, wbits, wmask, entA, valA, fwij, fm0, ffast, jf, ent_sm, ent_mx, ent_ck,
                                      lut, W, si, G, r, A.emask, c9, hit, mhit, po);
                 bool other = false;
 #pragma unroll
-                for (int u = 0; u < kUnroll; u++) {
+                for (int u = 0; u < kU; u++) {
                     other |= po[u] != 0;
                     if (seguA[u] < 0) continue;
                     if (seguA[u] != q) {
@@ -778,9 +781,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                     cj += hit[u];
                     cjm += mhit[u];
                 }
-                if (__ballot(other)) aggregate_other(po, lane, wcnt);
+                if (__ballot(other)) aggregate_other<kU>(po, lane, wcnt);
 #pragma unroll
-                for (int u = 0; u < kUnroll; u++) {
+                for (int u = 0; u < kU; u++) {
                     entA[u] = entB[u];
                     seguA[u] = seguB[u];
                 }
@@ -915,17 +918,17 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
         wave_lds_sync();
         wprobes += (unsigned long long)total;
         wstaged += (unsigned long long)d;
-        // the partner lists end to end, kUnroll consecutive entries per lane
+        // the partner lists end to end, kU consecutive entries per lane
         int qa = 0;                            // search cursor (monotone per lane)
         int q = -1;                            // segment whose counters this lane holds
         uint32_t cj = 0, cjm = 0;
         const int wtotal = (int)total;          // <= kWaveStreamMax
-        for (int fb = 0; fb < wtotal; fb += kWave * kUnroll) {
-            uint32_t ent4[kUnroll];
-            int seg4[kUnroll];
+        for (int fb = 0; fb < wtotal; fb += kWave * kU) {
+            uint32_t ent4[kU];
+            int seg4[kU];
 #pragma unroll
-            for (int u = 0; u < kUnroll; u++) {
-                const int f = fb + lane * kUnroll + u;
+            for (int u = 0; u < kU; u++) {
+                const int f = fb + lane * kU + u;
                 seg4[u] = -1;
                 ent4[u] = 0u;
                 if (f < wtotal) {
@@ -934,19 +937,19 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                     ent4[u] = gld(G.fadj + Wl.src[qa] + f);
                 }
             }
-            bool val4[kUnroll], hit[kUnroll], mhit[kUnroll];
-            uint32_t po[kUnroll];
+            bool val4[kU], hit[kU], mhit[kU];
+            uint32_t po[kU];
 #pragma unroll
-            for (int u = 0; u < kUnroll; u++) val4[u] = seg4[u] >= 0;
-            int fwij[kUnroll];
-            uint32_t fm0[kUnroll];
-            bool ffast[kUnroll];
+            for (int u = 0; u < kU; u++) val4[u] = seg4[u] >= 0;
+            int fwij[kU];
+            uint32_t fm0[kU];
+            bool ffast[kU];
             {
                 int qc = -1, cw = 0;
                 uint32_t cm = 0u;
                 bool cf = false;
 #pragma unroll
-                for (int u = 0; u < kUnroll; u++) {
+                for (int u = 0; u < kU; u++) {
                     const int qq = seg4[u] < 0 ? 0 : seg4[u];
                     if (qq != qc) {
                         qc = qq;
@@ -975,11 +978,11 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                 J.jr = (int32_t)(jent >> wbits);
                 return J;
             };
-            probe_tile<PER_EDGE>(Wl.tab, hbits, wbits, wmask, ent4, val4, fwij, fm0, ffast, jf, Wl.ent_sm, Wl.ent_mx,
+            probe_tile<kU, PER_EDGE>(Wl.tab, hbits, wbits, wmask, ent4, val4, fwij, fm0, ffast, jf, Wl.ent_sm, Wl.ent_mx,
                                  Wl.ent_ck, lut, W, si, G, r, A.emask, c9, hit, mhit, po);
             bool other = false;
 #pragma unroll
-            for (int u = 0; u < kUnroll; u++) {
+            for (int u = 0; u < kU; u++) {
                 other |= po[u] != 0;
                 if (seg4[u] < 0) continue;
                 if (seg4[u] != q) {
@@ -993,7 +996,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                 cj += hit[u];
                 cjm += mhit[u];
             }
-            if (__ballot(other)) aggregate_other(po, lane, wcnt);
+            if (__ballot(other)) aggregate_other<kU>(po, lane, wcnt);
         }
         if (q >= 0) {
             if (PER_WEDGE && cj) atomicAdd(&Wl.cj[q], cj);
