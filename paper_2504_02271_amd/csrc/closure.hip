@@ -677,24 +677,40 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
             // a wave takes 64*kU consecutive entries, kU per lane.
             // here total < nseg * 256 <= 65536: stream offsets fit in 32 bits
             const int total32 = (int)total;
+            // Middle-centric (short segments): each wave takes its own
+            // contiguous quarter of the stream (a multiple of 64*kU entries)
+            // and a lane's segment cursor moves forward by a linear scan.
+            // Owner-centric: the waves interleave steps over the whole stream
+            // and a lane finds its segment by binary search.
+            constexpr int kStep = kWave * kU;
+            constexpr int kWaves = kBlock / kWave;
+            const int per_wave = (total32 + kWaves * kStep - 1) / (kWaves * kStep) * kStep;
+            const int f_hi = MID ? min(total32, (wave + 1) * per_wave) : total32;
             int qa = -1;                   // address cursor
             int qa_end = 0;
             int64_t srca = 0;
             int q = -1;                    // segment whose counters this lane holds
             uint32_t cj = 0, cjm = 0;
-            const int stride = kBlock * kU;
+            const int stride = MID ? kStep : kBlock * kU;
             auto fetch = [&](int f0, uint32_t *ent, int *segu) {
 #pragma unroll
                 for (int u = 0; u < kU; u++) {
                     const int f = f0 + u;
                     segu[u] = -1;
                     int64_t addr = 0;
-                    if (f < total32) {
+                    if (f < f_hi) {
                         if (f >= qa_end) {
-                            int lo_s = qa < 0 ? 0 : qa + 1, hi_s = nseg;
-                            while (lo_s < hi_s) {
-                                int mid = (lo_s + hi_s) >> 1;
-                                if ((int)seg_pre[mid + 1] <= f) lo_s = mid + 1; else hi_s = mid;
+                            int lo_s;
+                            if (MID && qa >= 0) {
+                                lo_s = qa + 1;
+                                while ((int)seg_pre[lo_s + 1] <= f) lo_s++;   // stops below nseg: f < total
+                            } else {
+                                lo_s = qa < 0 ? 0 : qa + 1;
+                                int hi_s = nseg;
+                                while (lo_s < hi_s) {
+                                    int mid = (lo_s + hi_s) >> 1;
+                                    if ((int)seg_pre[mid + 1] <= f) lo_s = mid + 1; else hi_s = mid;
+                                }
                             }
                             qa = lo_s;
                             qa_end = (int)seg_pre[qa + 1];
@@ -706,15 +722,15 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                     ent[u] = segu[u] >= 0 ? gld(G.fadj + addr) : 0u;
                 }
             };
-            int fb = wave * kWave * kU;
+            int fb = MID ? wave * per_wave : wave * kStep;
             uint32_t entA[kU];
             int seguA[kU];
-            if (fb < total32) fetch(fb + lane * kU, entA, seguA);
-            for (; fb < total32; fb += stride) {
+            if (fb < f_hi) fetch(fb + lane * kU, entA, seguA);
+            for (; fb < f_hi; fb += stride) {
                 uint32_t entB[kU];
                 int seguB[kU];
                 const int fbn = fb + stride;
-                if (fbn < total32) {
+                if (fbn < f_hi) {
                     fetch(fbn + lane * kU, entB, seguB);
                 } else {
 #pragma unroll
