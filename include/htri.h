@@ -266,6 +266,31 @@ typedef struct {
 htri_status htri_estimate(htri_graph *g, const htri_sample_params *p, double est[21],
                           double stderr_[21], double *time_ms);
 
+/* Sub-hypergraph for sigma-sampling (Algorithm 6, with sigma in (0, 1]: the
+ * hyperedges are subsampled before the hyperwedges are, and the estimate is
+ * scaled back; Section 4.2).  Hyperedge x of g (normalised id) gets the
+ * 64-bit word number x of Philox-4x32-10 stream 4 under `seed` (counter
+ * (x lo, x hi, 4, 0), key (seed lo, seed hi)).
+ *   mode 0: x is kept when its word is below floor(sigma * 2^64) (all when
+ *           sigma = 1): each hyperedge independently with probability sigma.
+ *   mode 1: exactly n = floor(sigma * m + 1/2) hyperedges, those with the n
+ *           smallest words (equal words by id): a uniform n-subset.
+ * The hypergraph the kept hyperedges induce (same vertex ids, the flags,
+ * allocator and stream of g) is loaded as *out; its input order is the kept
+ * ids ascending.
+ *   kept_ids        NULL or host int32[m]: the kept normalised ids of g,
+ *                   ascending (num_kept of them).
+ *   num_kept        NULL or the number kept.
+ *   triangle_scale  NULL or the inverse of the probability that a given
+ *                   hyper-triangle of g keeps all three hyperedges:
+ *                   sigma^-3 (mode 0), m(m-1)(m-2) / (n(n-1)(n-2)) (mode 1;
+ *                   0 when n < 3).  Counts or estimates on *out times this
+ *                   are unbiased for g.
+ * Errors: HTRI_E_INVALID (sigma outside (0, 1], unknown mode, NULL out),
+ * HTRI_E_OOM, HTRI_E_DEVICE; *out is NULL on error. */
+htri_status htri_subgraph(htri_graph *g, double sigma, uint64_t seed, int32_t mode, htri_graph **out,
+                          int32_t *kept_ids, int64_t *num_kept, double *triangle_scale);
+
 /* Close an explicit list of wedges (indices into the htri_get_wedges order)
  * and return per-pattern closure counts, int64[n*21] host array (row w:
  * [0] total, [p] pattern p).  The sampling kernels' closure step. */

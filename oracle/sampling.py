@@ -101,3 +101,51 @@ def relative_error(est: np.ndarray, exact: np.ndarray):
     rel = np.full(20, np.nan)
     rel[nz] = np.abs(H[nz] - E[nz]) / H[nz]
     return float(np.nanmean(rel)) if nz.any() else 0.0, rel
+
+
+# ---------------------------------------------------------------- sigma-sampling
+
+SUBGRAPH_STREAM = 4
+
+
+def subgraph_select(m: int, sigma: float, seed: int, fixed_size: bool) -> np.ndarray:
+    """Kept hyperedge ids (normalised ids, ascending) of the sub-hypergraph of
+    Algorithm 6's sigma-sampling.  Hyperedge x gets the 64-bit word number x
+    of stream SUBGRAPH_STREAM.  Independent (fixed_size False): kept when the
+    word is below floor(sigma * 2^64), all when sigma = 1.  Fixed size: the
+    n = floor(sigma * m + 1/2) hyperedges with the smallest words, equal
+    words by id."""
+    if m == 0:
+        return np.zeros(0, np.int64)
+    u = draws_u64(seed, SUBGRAPH_STREAM, m)
+    if not fixed_size:
+        if sigma >= 1.0:
+            return np.arange(m, dtype=np.int64)
+        thr = np.uint64(int(sigma * 2.0 ** 64))
+        return np.nonzero(u < thr)[0].astype(np.int64)
+    n = int(np.floor(sigma * m + 0.5))
+    n = min(max(n, 0), m)
+    order = np.lexsort((np.arange(m), u))
+    return np.sort(order[:n]).astype(np.int64)
+
+
+def subgraph_scale(m: int, n: int, sigma: float, fixed_size: bool) -> float:
+    """Inverse of the probability that a given hyper-triangle keeps its three
+    hyperedges: sigma^-3 when each hyperedge is kept independently, the ratio
+    m(m-1)(m-2) / (n(n-1)(n-2)) for a uniform n-subset (0 when n < 3)."""
+    if not fixed_size:
+        return 1.0 / (sigma * sigma * sigma)
+    if n < 3:
+        return 0.0
+    M, N = float(m), float(n)
+    return (M * (M - 1.0) * (M - 2.0)) / (N * (N - 1.0) * (N - 2.0))
+
+
+def induced_csr(offsets: np.ndarray, members: np.ndarray, kept: np.ndarray):
+    """CSR of the hyperedges `kept` (in that order) of a CSR."""
+    sizes = (offsets[kept + 1] - offsets[kept]).astype(np.int64)
+    off = np.zeros(kept.shape[0] + 1, np.int64)
+    np.cumsum(sizes, out=off[1:])
+    mem = np.concatenate([members[offsets[x]:offsets[x + 1]] for x in kept]) if kept.shape[0] else \
+        np.zeros(0, np.int32)
+    return off, mem.astype(np.int32)

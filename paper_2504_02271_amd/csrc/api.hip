@@ -136,6 +136,34 @@ htri_status htri_graph_csr(const htri_graph *hc, int64_t *offsets, int32_t *memb
     });
 }
 
+htri_status htri_subgraph(htri_graph *h, double sigma, uint64_t seed, int32_t mode, htri_graph **out,
+                          int32_t *kept_ids, int64_t *num_kept, double *triangle_scale) {
+    if (!out) return HTRI_E_INVALID;
+    *out = nullptr;
+    if (!h || !(sigma > 0.0 && sigma <= 1.0) || (mode != 0 && mode != 1)) return HTRI_E_INVALID;
+    htri_graph *sub = nullptr;
+    try {
+        sub = new htri_graph();
+    } catch (...) {
+        return HTRI_E_OOM;
+    }
+    sub->g.stream = h->g.stream;
+    sub->g.al = h->g.al;
+    std::vector<int32_t> kept;
+    htri_status st = run(&h->g, [&] { htri::subgraph_select(h->g, sigma, seed, mode, sub->g, kept); });
+    if (st != HTRI_OK) {
+        (void)hipStreamSynchronize(h->g.stream);
+        delete sub;
+        return st;
+    }
+    const int64_t n = (int64_t)kept.size();
+    if (kept_ids && n) std::memcpy(kept_ids, kept.data(), sizeof(int32_t) * n);
+    if (num_kept) *num_kept = n;
+    if (triangle_scale) *triangle_scale = htri::subgraph_triangle_scale(h->g.m, n, sigma, mode);
+    *out = sub;
+    return HTRI_OK;
+}
+
 htri_status htri_build_wedges(htri_graph *h, int64_t summary[6]) {
     if (!h) return HTRI_E_INVALID;
     htri_status st = HTRI_OK;

@@ -299,6 +299,12 @@ void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21],
                     uint32_t *cw_dev /*nw or null*/);
 // fill the S entries of the last count's census (run on request)
 void closure_stream_stats(Graph &g);
+// subgraph.hip: the sub-hypergraph of sigma-sampling (kept: normalised ids
+// in g of the kept hyperedges, ascending); out must carry g's stream and
+// allocator
+int64_t subgraph_fixed_size(int64_t m, double sigma);
+double subgraph_triangle_scale(int64_t m, int64_t n, double sigma, int mode);
+void subgraph_select(Graph &g, double sigma, uint64_t seed, int mode, Graph &out, std::vector<int32_t> &kept);
 // sample.hip: closure of explicit wedges (per-sample counts) and weighted
 // sums over uniform (mode 1) or pool (mode 2) draws
 void close_wedge_list_counts(Graph &g, const int64_t *dev_idx, int64_t n, int64_t *dev_out);

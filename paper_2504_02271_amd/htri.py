@@ -111,6 +111,7 @@ def load_library() -> ctypes.CDLL:
         f.restype = res
     _optional = {
         "htri_estimate": ([_P, ctypes.POINTER(SampleParams), _P, _P, _P], ctypes.c_int),
+        "htri_subgraph": ([_P, ctypes.c_double, _u64, _i32, ctypes.POINTER(_P), _P, _P, _P], ctypes.c_int),
         "htri_close_wedges": ([_P, _P, _i64, _P], ctypes.c_int),
         "htri_wedge_features": ([_P, _P], ctypes.c_int),
         "htri_model_create": ([_u64, _P, ctypes.POINTER(_P)], ctypes.c_int),
@@ -247,6 +248,20 @@ class Graph:
         om = np.zeros(nw, np.int32)
         _check(self._lib.htri_get_wedges(self._h, _ptr(src), _ptr(dst), _ptr(om)), "htri_get_wedges", self._h)
         return src, dst, om
+
+    def subgraph(self, sigma: float, seed: int = 0, fixed_size: bool = False):
+        """Sub-hypergraph for sigma-sampling: (Graph, kept normalised ids
+        ascending, triangle scale).  fixed_size: exactly round(sigma*m)
+        hyperedges, else each kept with probability sigma.  Counts or
+        estimates on the subgraph times the scale are unbiased here."""
+        kept = np.zeros(max(self.num_edges, 1), np.int32)
+        n = ctypes.c_int64(0)
+        scale = ctypes.c_double(0.0)
+        h = ctypes.c_void_p()
+        _check(self._lib.htri_subgraph(self._h, float(sigma), int(seed) & (2**64 - 1), 1 if fixed_size else 0,
+                                       ctypes.byref(h), _ptr(kept), ctypes.byref(n), ctypes.byref(scale)),
+               "htri_subgraph", self._h)
+        return Graph(h, self._mem), kept[: n.value].copy(), float(scale.value)
 
     def get_wedge_list(self, idx) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
         """(src, dst, omega) of the listed hyperwedges (indices in get_wedges order)."""
