@@ -120,6 +120,7 @@ def estimator_study(seeds: int, log_fn):
                                     log=log_fn, exact_inclusion=True)
     for r in rows + rows_x:
         r["learned_wins"] = r["learned_rel_err"] < r["uniform_rel_err"]
+    rows_sigma = learn.sigma_study(G, exact, sigmas=(1.0, 0.5, 0.25), seeds=8, budget=0.01, log=log_fn)
     return {
         "eval_workload": "tags-shaped evaluation graph: as the exact workload with seed 5 "
                          f"({G.num_wedges} hyperwedges)",
@@ -136,6 +137,13 @@ def estimator_study(seeds: int, log_fn):
         "exact_inclusion": "second study: both samplers close every inclusion hyperwedge exactly (a few "
                            "thousand) and sample only the intersection-type ones (separate sampling of the "
                            "two hyperwedge types, as in Appro-adv, with the inclusion stratum exhausted)",
+        "sigma_sampling": {
+            "what": "Appro-bs with sigma: a uniform subset of floor(sigma*m+1/2) hyperedges, 1% of the induced "
+                    "subgraph's hyperwedges sampled uniformly, the estimate times m(m-1)(m-2)/(n(n-1)(n-2)); "
+                    "8 seeds; ms = selection + load + hyperwedges + estimate (wall clock); "
+                    "subgraph_exact_rel_err = the subgraph's exact count scaled the same way",
+            "rows": rows_sigma,
+        },
     }
 
 
