@@ -1459,6 +1459,7 @@ constexpr int kWinRowsMax = (int)kWindowRowsMax;
 constexpr int kWinWordsMax = kWinRowsMax / 32;
 constexpr int kWinClasses = 8;              // bulk-counted classes at most (fewer for wide windows)
 constexpr int kWinLdsBudget = 60 * 1024;    // bytes of row bitmaps per block of k_close_window
+constexpr int kEnumQ = 64;                  // queued hits per wave in k_close_window
 
 // exclusive prefix of popcounts of x[0..n) into out (n up to kWinWordsMax),
 // whole block, contiguous chunks per thread
@@ -1548,6 +1549,7 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
     __shared__ int32_t wsum[kBlock / kWave];
     __shared__ unsigned long long cnt[21];
     __shared__ int sh_row, sh_nc;
+    __shared__ uint64_t enumq[(kBlock / kWave) * kEnumQ];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const GraphDesc &G = A.G;
     const int wbits = G.wbits;
@@ -1652,53 +1654,103 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
             __threadfence();
             __syncthreads();
         }
+        // Hits outside the bulk-counted classes, (position in N+(r), position
+        // in N+(j), partner) with 17 bits each, wait in the wave's queue and
+        // are classified one lane per hit when the queue fills and after the
+        // last partner, so that their dependent loads run side by side.
+        uint64_t *Q = enumq + wave * kEnumQ;
+        int qn = 0;                                   // wave-uniform
+        auto classify_hit = [&](int pr, int pj, int qq) {
+            const uint32_t jent = gld(G.fadj + base + qq);
+            const int32_t j = (int32_t)(jent >> wbits);
+            const int wij = (int)(jent & wmask);
+            const int sj = gld(G.esize + j);
+            const int64_t jbase = gld(G.fptr + j);
+            const uint32_t kent = gld(G.fadj + base + pr);
+            const int32_t k = (int32_t)(kent >> wbits);
+            const int wik = (int)(kent & wmask);
+            const int wjk = (int)(gld(G.fadj + jbase + pj) & wmask);
+            const int sk = gld(G.esize + k);
+            int g;
+            if (W > 0) {
+                g = 0;
+                for (int x = 0; x < W; x++)
+                    g += __popc(gld(G.fmask + mbase + (int64_t)qq * W + x) & gld(G.fmask + mbase + (int64_t)pr * W + x));
+            } else {
+                g = triple_common(G.eptr, G.emem, r, j, k);
+            }
+            const uint32_t p = A.lut[region_mask(si, sj, sk, wij, wik, wjk, g)];
+            atomicAdd(&cnt[p], 1ull);
+            enumerated++;
+            if (PER_EDGE && ((A.emask >> p) & 1u)) {
+                atomicAdd(&A.cwkm[base + pr], 1u);
+                atomicAdd(&A.cwjm[base + qq], 1u);
+            }
+        };
+        auto flush = [&]() {
+            wave_lds_sync();
+            if (lane < qn) {
+                const uint64_t e = Q[lane];
+                classify_hit((int)(e & 0x1FFFFu), (int)((e >> 17) & 0x1FFFFu), (int)(e >> 34));
+            }
+            wave_lds_sync();
+            qn = 0;
+        };
         // partners: entries 0 .. d-2, one wave each
         for (int q = wave; q < d - 1; q += kBlock / kWave) {
             const uint32_t jent = gld(G.fadj + base + q);
             const int32_t j = (int32_t)(jent >> wbits);
             const int jr = j - (int32_t)A.w0;
-            const int wij = (int)(jent & wmask);
-            const int sj = gld(G.esize + j);
-            uint32_t mj[kMaskWordsMax] = {0u, 0u, 0u, 0u};
-            for (int w = 0; w < W; w++) mj[w] = gld(G.fmask + mbase + (int64_t)q * W + w);
             const int cj = class_of(jent, q);
             const bool dom = cj >= 0;
-            const int64_t jbase = gld(G.fptr + j);
             const uint32_t *bfj = A.bf + (int64_t)jr * nwords;
             const uint32_t *bf1j = A.bf1 + (int64_t)jr * nwords;
             const uint32_t *pfj = A.pf + (int64_t)jr * nwords;
-            uint32_t all = 0, fast = 0, menum = 0;
-            for (int w = (jr >> 5) + lane; w < nwords; w += kWave) {
-                const uint32_t bw = gld(bfj + w);
-                const uint32_t a = BR[w] & bw;
-                all += __popc(a);
-                const uint32_t fs = dom ? (BK(cj)[w] & gld(bf1j + w)) : 0u;
-                fast += __popc(fs);
-                uint32_t non = a & ~fs;
-                while (non) {
-                    const int bpos = __ffs(non) - 1;
-                    non &= non - 1;
-                    const uint32_t below = (1u << bpos) - 1u;
-                    const int pr = PR[w] + __popc(BR[w] & below);          // position of k in N+(r)
-                    const int pj = (int)gld(pfj + w) + __popc(bw & below); // position of k in N+(j)
-                    const uint32_t kent = gld(G.fadj + base + pr);
-                    const int32_t k = (int32_t)(kent >> wbits);
-                    const int wik = (int)(kent & wmask);
-                    const int wjk = (int)(gld(G.fadj + jbase + pj) & wmask);
-                    const int sk = gld(G.esize + k);
-                    int g;
-                    if (W > 0) {
-                        g = 0;
-                        for (int x = 0; x < W; x++) g += __popc(mj[x] & gld(G.fmask + mbase + (int64_t)pr * W + x));
-                    } else {
-                        g = triple_common(G.eptr, G.emem, r, j, k);
+            uint32_t all = 0, fast = 0;
+            for (int wb = (jr >> 5); wb < nwords; wb += kWave) {
+                const int w = wb + lane;
+                uint32_t bw = 0u, a = 0u, non = 0u;
+                if (w < nwords) {
+                    bw = gld(bfj + w);
+                    a = BR[w] & bw;
+                    all += __popc(a);
+                    const uint32_t fs = dom ? (BK(cj)[w] & gld(bf1j + w)) : 0u;
+                    fast += __popc(fs);
+                    non = a & ~fs;
+                }
+                if (!__ballot(non != 0u)) continue;
+                const int c = __popc(non);
+                int incl = c;
+#pragma unroll
+                for (int o = 1; o < kWave; o <<= 1) {
+                    const int t = __shfl_up(incl, o, kWave);
+                    if (lane >= o) incl += t;
+                }
+                const int total = __shfl(incl, kWave - 1, kWave);
+                if (qn + total > kEnumQ) flush();
+                if (total <= kEnumQ) {
+                    int slot = qn + incl - c;
+                    if (non) {
+                        const int pr0 = PR[w];
+                        const uint32_t brw = BR[w];
+                        const int pj0 = (int)gld(pfj + w);
+                        while (non) {
+                            const int bpos = __ffs(non) - 1;
+                            non &= non - 1;
+                            const uint32_t below = (1u << bpos) - 1u;
+                            const uint64_t pr = (uint64_t)(pr0 + __popc(brw & below));   // position of k in N+(r)
+                            const uint64_t pj = (uint64_t)(pj0 + __popc(bw & below));    // position of k in N+(j)
+                            Q[slot++] = pr | (pj << 17) | ((uint64_t)q << 34);
+                        }
                     }
-                    const uint32_t p = A.lut[region_mask(si, sj, sk, wij, wik, wjk, g)];
-                    atomicAdd(&cnt[p], 1ull);
-                    enumerated++;
-                    if (PER_EDGE && ((A.emask >> p) & 1u)) {
-                        menum++;
-                        atomicAdd(&A.cwkm[base + pr], 1u);
+                    qn += total;
+                } else {
+                    // more hits in this step than the queue holds: classify them in place
+                    while (non) {
+                        const int bpos = __ffs(non) - 1;
+                        non &= non - 1;
+                        const uint32_t below = (1u << bpos) - 1u;
+                        classify_hit(PR[w] + __popc(BR[w] & below), (int)gld(pfj + w) + __popc(bw & below), q);
                     }
                 }
             }
@@ -1707,14 +1759,15 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
             for (int o = kWave / 2; o > 0; o >>= 1) {
                 all += __shfl_xor(all, o, kWave);
                 fast += __shfl_xor(fast, o, kWave);
-                menum += __shfl_xor(menum, o, kWave);
             }
             if (lane == 0) {
                 if (fast) atomicAdd(&cnt[kPatternCommonVertex], (unsigned long long)fast);
                 if (PER_WEDGE) A.cwj[base + q] = all;
-                if (PER_EDGE) A.cwjm[base + q] = (count9 ? fast : 0u) + menum;
+                // the enumerated hits add theirs when they are classified
+                if (PER_EDGE && count9 && fast) atomicAdd(&A.cwjm[base + q], fast);
             }
         }
+        if (qn > 0) flush();
     }
     __syncthreads();
     if (tid >= 1 && tid < 21 && cnt[tid]) atomicAdd(&A.counts[tid], cnt[tid]);
