@@ -1636,20 +1636,28 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
         }
         __syncthreads();
         // k-role of the common-vertex triangles: for k in class c, |K_c & BI1_k|
+        // (16 lanes per entry, four entries per wave: the word ranges are often short)
         if (PER_EDGE) {
-            for (int q = wave; q < d; q += kBlock / kWave) {
-                const uint32_t ent = gld(G.fadj + base + q);
-                const int kr = (int)((int64_t)(ent >> wbits) - A.w0);
-                const int c = count9 ? class_of(ent, q) : -1;
+            constexpr int kGroup = 16;
+            const int sub = lane / kGroup, gl = lane % kGroup;
+            for (int qb = wave * (kWave / kGroup); qb < d; qb += kBlock / kGroup) {
+                const int q = qb + sub;
                 uint32_t kf = 0;
-                if (c >= 0) {
-                    const uint32_t *bik = A.bi1 + (int64_t)kr * nwords;
-                    for (int w = (row >> 5) + lane; w <= (kr >> 5); w += kWave) kf += __popc(BK(c)[w] & gld(bik + w));
-                    words_read += (unsigned long long)((kr >> 5) - (row >> 5) + 1);
-#pragma unroll
-                    for (int o = kWave / 2; o > 0; o >>= 1) kf += __shfl_xor(kf, o, kWave);
+                unsigned long long rg = 0;
+                if (q < d) {
+                    const uint32_t ent = gld(G.fadj + base + q);
+                    const int kr = (int)((int64_t)(ent >> wbits) - A.w0);
+                    const int c = count9 ? class_of(ent, q) : -1;
+                    if (c >= 0) {
+                        const uint32_t *bik = A.bi1 + (int64_t)kr * nwords;
+                        for (int w = (row >> 5) + gl; w <= (kr >> 5); w += kGroup) kf += __popc(BK(c)[w] & gld(bik + w));
+                        rg = (unsigned long long)((kr >> 5) - (row >> 5) + 1);
+                    }
                 }
-                if (lane == 0) A.cwkm[base + q] = kf;
+#pragma unroll
+                for (int o = kGroup / 2; o > 0; o >>= 1) kf += __shfl_xor(kf, o, kWave);
+                words_read += __shfl(rg, 0, kWave) + __shfl(rg, 16, kWave) + __shfl(rg, 32, kWave) + __shfl(rg, 48, kWave);
+                if (gl == 0 && q < d) A.cwkm[base + q] = kf;
             }
             __threadfence();
             __syncthreads();
