@@ -1668,7 +1668,9 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
         // last partner, so that their dependent loads run side by side.
         uint64_t *Q = enumq + wave * kEnumQ;
         int qn = 0;                                   // wave-uniform
-        auto classify_hit = [&](int pr, int pj, int qq) {
+        // classify one hit; returns whether it counts in the per-hyperedge
+        // counts (its k-role is added here, its j-role by the caller)
+        auto classify_hit = [&](int pr, int pj, int qq) -> bool {
             const uint32_t jent = gld(G.fadj + base + qq);
             const int32_t j = (int32_t)(jent >> wbits);
             const int wij = (int)(jent & wmask);
@@ -1690,16 +1692,32 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
             const uint32_t p = A.lut[region_mask(si, sj, sk, wij, wik, wjk, g)];
             atomicAdd(&cnt[p], 1ull);
             enumerated++;
-            if (PER_EDGE && ((A.emask >> p) & 1u)) {
-                atomicAdd(&A.cwkm[base + pr], 1u);
-                atomicAdd(&A.cwjm[base + qq], 1u);
-            }
+            const bool counted = PER_EDGE && ((A.emask >> p) & 1u);
+            if (counted) atomicAdd(&A.cwkm[base + pr], 1u);
+            return counted;
         };
+        // The queue is in partner order: the j-role counts of a run of equal
+        // partners go out as one atomic, from the run's last lane.
         auto flush = [&]() {
             wave_lds_sync();
+            int qq = -1;
+            bool counted = false;
             if (lane < qn) {
                 const uint64_t e = Q[lane];
-                classify_hit((int)(e & 0x1FFFFu), (int)((e >> 17) & 0x1FFFFu), (int)(e >> 34));
+                qq = (int)(e >> 34);
+                counted = classify_hit((int)(e & 0x1FFFFu), (int)((e >> 17) & 0x1FFFFu), qq);
+            }
+            if (PER_EDGE) {
+                const int qprev = __shfl_up(qq, 1, kWave);
+                const int qnext = __shfl_down(qq, 1, kWave);
+                const uint64_t starts = __ballot(lane < qn && (lane == 0 || qprev != qq));
+                const uint64_t cm = __ballot(counted);
+                if (lane < qn && (lane == qn - 1 || qnext != qq)) {
+                    const uint64_t upto = (2ull << lane) - 1ull;   // lanes 0 .. lane (all 64 for lane 63)
+                    const int s0 = 63 - __clzll(starts & upto);
+                    const uint32_t n = (uint32_t)__popcll(cm & upto & ~((1ull << s0) - 1ull));
+                    if (n) atomicAdd(&A.cwjm[base + qq], n);
+                }
             }
             wave_lds_sync();
             qn = 0;
@@ -1758,7 +1776,8 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
                         const int bpos = __ffs(non) - 1;
                         non &= non - 1;
                         const uint32_t below = (1u << bpos) - 1u;
-                        classify_hit(PR[w] + __popc(BR[w] & below), (int)gld(pfj + w) + __popc(bw & below), q);
+                        if (classify_hit(PR[w] + __popc(BR[w] & below), (int)gld(pfj + w) + __popc(bw & below), q))
+                            atomicAdd(&A.cwjm[base + q], 1u);
                     }
                 }
             }
