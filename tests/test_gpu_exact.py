@@ -162,6 +162,28 @@ def test_heavy_clique_multichunk_and_wide_edges(htri):
     assert hub > 1000 and counts[0] >= math.comb(hub, 3)
 
 
+def test_partial_window_with_middle_probing(htri):
+    """A dense hub (1,100 hyperedges through vertex 0) over a sparse
+    background: the top 2,048 ranks form the dense window and the other
+    owners are probed around the middle, with middles inside the window (the
+    window's per-hyperedge counters receive the probing's k-role counts)."""
+    rng = np.random.default_rng(21)
+    edges = []
+    for x in range(1100):
+        extra = rng.choice(np.arange(1, 400), size=int(rng.integers(1, 4)), replace=False)
+        edges.append([0] + sorted(extra.tolist()))
+    for x in range(3900):
+        edges.append(sorted(rng.choice(np.arange(400, 20000), size=3, replace=False).tolist()))
+    for x in range(200):   # links between the hub's vertices and the background
+        edges.append(sorted([int(rng.integers(1, 400))] + rng.choice(np.arange(400, 20000), size=2,
+                                                                       replace=False).tolist()))
+    g = synth.from_lists(edges, 20000, "partial-window")
+    G, o, counts = check_exact(htri, g, wedge_sample=20000, windows=("auto",))
+    G.count_patterns(per_edge=True, window="auto")
+    st = G.closure_stats()
+    assert st[5] == 2048 and 0 < st[8] < G.num_wedges and st[12] == 1, st
+
+
 def test_empty_and_wedgeless(htri):
     g = synth.from_lists([], 5, "empty")
     G = htri.graph_load(g.offsets, g.members, 5)
