@@ -1460,6 +1460,7 @@ constexpr int kWinWordsMax = kWinRowsMax / 32;
 constexpr int kWinClasses = 8;              // bulk-counted classes at most (fewer for wide windows)
 constexpr int kWinLdsBudget = 60 * 1024;    // bytes of row bitmaps per block of k_close_window
 constexpr int kEnumQ = 64;                  // queued hits per wave in k_close_window
+constexpr int kWinPartners = 8;             // partners closed side by side per wave
 
 // exclusive prefix of popcounts of x[0..n) into out (n up to kWinWordsMax),
 // whole block, contiguous chunks per thread
@@ -1636,9 +1637,9 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
         }
         __syncthreads();
         // k-role of the common-vertex triangles: for k in class c, |K_c & BI1_k|
-        // (16 lanes per entry, four entries per wave: the word ranges are often short)
+        // (8 lanes per entry, eight entries per wave: the word ranges are often short)
         if (PER_EDGE) {
-            constexpr int kGroup = 16;
+            constexpr int kGroup = 8;
             const int sub = lane / kGroup, gl = lane % kGroup;
             for (int qb = wave * (kWave / kGroup); qb < d; qb += kBlock / kGroup) {
                 const int q = qb + sub;
@@ -1656,7 +1657,8 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
                 }
 #pragma unroll
                 for (int o = kGroup / 2; o > 0; o >>= 1) kf += __shfl_xor(kf, o, kWave);
-                words_read += __shfl(rg, 0, kWave) + __shfl(rg, 16, kWave) + __shfl(rg, 32, kWave) + __shfl(rg, 48, kWave);
+#pragma unroll
+                for (int g2 = 0; g2 < kWave / kGroup; g2++) words_read += __shfl(rg, g2 * kGroup, kWave);
                 if (gl == 0 && q < d) A.cwkm[base + q] = kf;
             }
             __threadfence();
@@ -1722,19 +1724,32 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
             wave_lds_sync();
             qn = 0;
         };
-        // partners: entries 0 .. d-2, one wave each
-        for (int q = wave; q < d - 1; q += kBlock / kWave) {
-            const uint32_t jent = gld(G.fadj + base + q);
-            const int32_t j = (int32_t)(jent >> wbits);
-            const int jr = j - (int32_t)A.w0;
-            const int cj = class_of(jent, q);
+        // partners: entries 0 .. d-2, kWinPartners per wave (kPG lanes each:
+        // the partners' set-up loads overlap and short rows fill the lanes)
+        constexpr int kPG = kWave / kWinPartners;
+        const int psub = lane / kPG, pl = lane % kPG;
+        for (int qb = wave * kWinPartners; qb < d - 1; qb += (kBlock / kWave) * kWinPartners) {
+            const int q = qb + psub;
+            const bool qv = q < d - 1;
+            uint32_t jent = 0u;
+            int jr = nwords * 32, cj = -1;
+            if (qv) {
+                jent = gld(G.fadj + base + q);
+                jr = (int)((jent >> wbits) - (uint32_t)A.w0);
+                cj = class_of(jent, q);
+            }
             const bool dom = cj >= 0;
-            const uint32_t *bfj = A.bf + (int64_t)jr * nwords;
-            const uint32_t *bf1j = A.bf1 + (int64_t)jr * nwords;
-            const uint32_t *pfj = A.pf + (int64_t)jr * nwords;
+            const uint32_t *bfj = A.bf + (int64_t)(qv ? jr : 0) * nwords;
+            const uint32_t *bf1j = A.bf1 + (int64_t)(qv ? jr : 0) * nwords;
+            const uint32_t *pfj = A.pf + (int64_t)(qv ? jr : 0) * nwords;
+            const int wfirst = qv ? (jr >> 5) : nwords;
+            int wmin = wfirst;              // the wave's loop covers every group's row
+#pragma unroll
+            for (int g2 = 1; g2 < kWinPartners; g2++) wmin = min(wmin, __shfl(wfirst, g2 * kPG, kWave));
+            const int span = nwords - __shfl(wmin, 0, kWave);
             uint32_t all = 0, fast = 0;
-            for (int wb = (jr >> 5); wb < nwords; wb += kWave) {
-                const int w = wb + lane;
+            for (int t0 = 0; t0 < span; t0 += kPG) {
+                const int w = wfirst + t0 + pl;
                 uint32_t bw = 0u, a = 0u, non = 0u;
                 if (w < nwords) {
                     bw = gld(bfj + w);
@@ -1781,13 +1796,15 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
                     }
                 }
             }
-            words_read += (unsigned long long)(nwords - (jr >> 5)) * (dom ? 2u : 1u);
+            const unsigned long long rg = qv ? (unsigned long long)(nwords - (jr >> 5)) * (dom ? 2u : 1u) : 0ull;
 #pragma unroll
-            for (int o = kWave / 2; o > 0; o >>= 1) {
+            for (int g2 = 0; g2 < kWinPartners; g2++) words_read += __shfl(rg, g2 * kPG, kWave);
+#pragma unroll
+            for (int o = kPG / 2; o > 0; o >>= 1) {
                 all += __shfl_xor(all, o, kWave);
                 fast += __shfl_xor(fast, o, kWave);
             }
-            if (lane == 0) {
+            if (pl == 0 && qv) {
                 if (fast) atomicAdd(&cnt[kPatternCommonVertex], (unsigned long long)fast);
                 if (PER_WEDGE) A.cwj[base + q] = all;
                 // the enumerated hits add theirs when they are classified
