@@ -73,7 +73,7 @@ typedef enum {
     HTRI_E_DEVICE = -6,           /* a HIP runtime error                      */
     HTRI_E_OVERFLOW = -7,         /* counts could exceed int64                */
     HTRI_E_STATE = -8,            /* call order (e.g. count before wedges)    */
-    HTRI_E_UNSUPPORTED = -9       /* size beyond what this build handles      */
+    HTRI_E_UNSUPPORTED = -9       /* size beyond what the library handles     */
 } htri_status;
 
 typedef struct htri_graph htri_graph;
