@@ -353,22 +353,26 @@ struct CloseBlockLds {
 };
 // Owner-centric wave items take the partner data from the chunk arrays
 // (partner q is entry q of N+(r)); middle-centric ones keep it apart in
-// p_sm / p_mx / p_ent, with p_ent = (rank of r) << wbits | omega_jr.
+// p_sm / p_ent, with p_ent = (rank of r) << wbits | omega_jr.  Middle-centric
+// wave items hash up to kWaveMidHashMax entries and have at most one Omega
+// word (the item builder sends the others to block items), so their extra
+// mask words are not kept.
 template <bool MID>
 struct CloseWaveLds {
-    uint2 tab[4 * kWaveOwnerMax];
-    uint2 ent_sm[kWaveOwnerMax];                       // (|e_k|, Omega word 0 of the hashed entry)
-    uint32_t ent_mx[kWaveOwnerMax * (kMaskWordsMax - 1)];
-    uint32_t ent_ck[kWaveOwnerMax];
+    static constexpr int kHash = MID ? kWaveMidHashMax : kWaveOwnerMax;
+    uint2 tab[4 * kHash];
+    uint2 ent_sm[kHash];                               // (|e_k|, Omega word 0 of the hashed entry)
+    uint32_t ent_mx[MID ? 4 : kWaveOwnerMax * (kMaskWordsMax - 1)];
+    uint32_t ent_ck[kHash];
     int64_t src[kWaveOwnerMax];                        // partner segment start minus its stream offset
-    uint32_t ent[kWaveOwnerMax];                       // packed entry (rank, omega) of the hashed list
+    uint32_t ent[kHash];                               // packed entry (rank, omega) of the hashed list
     int32_t incl[kWaveOwnerMax];                       // end of each partner segment in the stream
     uint32_t cj[kWaveOwnerMax];
     uint32_t cjm[kWaveOwnerMax];
     uint2 p_sm[MID ? kWaveOwnerMax : 2];               // (|e_r|, Omega_jr word 0)
-    uint32_t p_mx[MID ? kWaveOwnerMax * (kMaskWordsMax - 1) : 4];
+    uint32_t p_mx[4];                                  // (no extra Omega words in wave items)
     uint32_t p_ent[MID ? kWaveOwnerMax : 4];
-    int32_t jmem[MID ? 32 * kMaskWordsMax : 4];        // e_j's members (hyperedges with stored masks)
+    int32_t jmem[MID ? 32 : 4];                        // e_j's members (at most 32 when stored)
 };
 template <int CAP, int JP, bool PE, bool PW, bool MID>
 union CloseLds {
@@ -875,7 +879,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
         const int64_t mbase = gld(G.mptr + r);
         int hbits = 6;
         while ((1 << hbits) < 4 * d) hbits++;
-        const int H = 1 << hbits;              // <= 4 * kWaveOwnerMax
+        const int H = 1 << hbits;              // <= 4 * CloseWaveLds<MID>::kHash
         wave_lds_sync();                       // the previous owner's reads are done
         for (int t = lane; t < H; t += kWave) Wl.tab[t] = make_uint2(0u, kEmptyPos);
         if (MID && W > 0) {
@@ -890,18 +894,19 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
         int64_t my_wedge = 0;
         Wl.cj[lane] = 0;
         Wl.cjm[lane] = 0;
-        if (lane < d) {
-            const uint32_t ent = gld(G.fadj + base + lane);
+        for (int t = lane; t < d; t += kWave) {
+            const uint32_t ent = gld(G.fadj + base + t);
             const uint32_t k = ent >> wbits;
-            const int64_t mo = mbase + (int64_t)lane * W;
-            Wl.ent_sm[lane] = make_uint2((uint32_t)gld(G.esize + k), W > 0 ? gld(G.fmask + mo) : 0u);
-            for (int w = 1; w < W; w++) Wl.ent_mx[lane * (kMaskWordsMax - 1) + (w - 1)] = gld(G.fmask + mo + w);
-            Wl.ent[lane] = ent;
-            if (PER_EDGE) Wl.ent_ck[lane] = 0;
+            const int64_t mo = mbase + (int64_t)t * W;
+            Wl.ent_sm[t] = make_uint2((uint32_t)gld(G.esize + k), W > 0 ? gld(G.fmask + mo) : 0u);
+            if (!MID)
+                for (int w = 1; w < W; w++) Wl.ent_mx[t * (kMaskWordsMax - 1) + (w - 1)] = gld(G.fmask + mo + w);
+            Wl.ent[t] = ent;
+            if (PER_EDGE) Wl.ent_ck[t] = 0;
             uint32_t slot = hslot(k, hbits - 1) * 2;
-            while (atomicCAS(&Wl.tab[slot].y, kEmptyPos, (uint32_t)lane) != kEmptyPos) slot = (slot + 1) & (H - 1);
+            while (atomicCAS(&Wl.tab[slot].y, kEmptyPos, (uint32_t)t) != kEmptyPos) slot = (slot + 1) & (H - 1);
             Wl.tab[slot].x = ent;
-            if (!MID && lane < d - 1) {
+            if (!MID && t < d - 1) {
                 a = gld(G.fptr + k);
                 len = gld(G.fptr + k + 1) - a;
             }
@@ -913,10 +918,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
             len = (int64_t)(E.y >> wbits);
             uint32_t o0 = 0u, o1 = 0u, o2 = 0u, o3 = 0u;
             if (W > 0) entry_mask(G, E, wbits, Wl.jmem, si, o0, o1, o2, o3);
-            Wl.p_sm[lane] = make_uint2(E.w & wmask, o0);
-            Wl.p_mx[lane * (kMaskWordsMax - 1) + 0] = o1;
-            Wl.p_mx[lane * (kMaskWordsMax - 1) + 1] = o2;
-            Wl.p_mx[lane * (kMaskWordsMax - 1) + 2] = o3;
+            Wl.p_sm[lane] = make_uint2(E.w & wmask, o0);   // W <= 1: o1..o3 are 0
             Wl.p_ent[lane] = (E.w & ~wmask) | (E.y & wmask);   // (r << wbits) | omega_rj
             my_wedge = i;
         }
@@ -1025,10 +1027,11 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                 if (PER_WEDGE) A.cwj[e] = Wl.cj[lane];
                 if (PER_EDGE) A.cwjm[e] = Wl.cjm[lane];
             }
-            if (PER_EDGE && lane < d) {
-                if (!MID || (int64_t)r < A.kdirect_end) A.cwkm[base + lane] = Wl.ent_ck[lane];
-                else if (Wl.ent_ck[lane]) atomicAdd(&A.cwkm[base + lane], Wl.ent_ck[lane]);
-            }
+            if (PER_EDGE)
+                for (int t = lane; t < d; t += kWave) {
+                    if (!MID || (int64_t)r < A.kdirect_end) A.cwkm[base + t] = Wl.ent_ck[t];
+                    else if (Wl.ent_ck[t]) atomicAdd(&A.cwkm[base + t], Wl.ent_ck[t]);
+                }
         }
     }
     if (lane == 0 && wprobes) atomicAdd(A.probes, wprobes);
@@ -1284,18 +1287,18 @@ __global__ void k_inlist_fill(const int64_t *fptr, const uint32_t *fadj, int wbi
 
 // Middle-centric work items per middle j (at least one forward entry and one
 // in-list entry): wcnt = 1 for a middle closed by one wave (at most
-// kWaveOwnerMax forward entries and in-list entries, and at most
-// kWaveStreamMax streamed entries), else one block item per chunk of N+(j)
-// and piece of jp in-list entries.
-__global__ void k_item_counts_mid(const int64_t *fptr, const int64_t *iptr, const uint4 *inl, int wbits, int64_t m,
-                                  int cap, int jp, int64_t *cnt, int64_t *wcnt) {
+// kWaveMidHashMax forward entries, at most kWaveOwnerMax in-list entries, at
+// most one Omega word, and at most kWaveStreamMax streamed entries), else
+// one block item per chunk of N+(j) and piece of jp in-list entries.
+__global__ void k_item_counts_mid(const int64_t *fptr, const int64_t *iptr, const uint4 *inl, const int32_t *esize,
+                                  int wbits, int64_t m, int cap, int jp, int64_t *cnt, int64_t *wcnt) {
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += (int64_t)gridDim.x * blockDim.x) {
         const int64_t d = fptr[j + 1] - fptr[j];
         const int64_t nin = iptr[j + 1] - iptr[j];
         int64_t c = 0;
         bool wave = false;
         if (d >= 1 && nin >= 1) {
-            if (d <= kWaveOwnerMax && nin <= kWaveOwnerMax) {
+            if (d <= kWaveMidHashMax && nin <= kWaveOwnerMax && mask_words(esize[j]) <= 1) {
                 int64_t sz = 0;
                 for (int64_t p = iptr[j]; p < iptr[j + 1]; p++) sz += (int64_t)(inl[p].y >> wbits);
                 wave = sz <= kWaveStreamMax;
@@ -1427,7 +1430,7 @@ void build_items_mid(Graph &g, int32_t gid, const CloseConfig &cfg, const InList
     DBuf<int64_t> icnt(g.al, m + 1), wcnt(g.al, m + 1);
     if (m > 0) {
         hipLaunchKernelGGL(k_item_counts_mid, dim3(grid_for(m, 256)), dim3(256), 0, s, g.fptr.p, in.iptr.p, in.inl.p,
-                           g.wbits, m, cfg.cap, cfg.jp, icnt.p, wcnt.p);
+                           g.esize.p, g.wbits, m, cfg.cap, cfg.jp, icnt.p, wcnt.p);
         HTRI_LAUNCH_CHECK();
     }
     items_from_counts(g, icnt, wcnt, out, [&] {

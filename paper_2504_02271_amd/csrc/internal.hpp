@@ -246,6 +246,10 @@ struct CloseArgs {
 // Owners with at most kWaveOwnerMax forward entries whose partner lists hold
 // at most kWaveStreamMax entries in total are closed by one wave each.
 constexpr int kWaveOwnerMax = 64;
+// Middle-centric single-middle items: up to kWaveMidHashMax entries of N+(j)
+// (and at most kWaveOwnerMax in-list entries) when e_j needs at most one
+// Omega word.
+constexpr int kWaveMidHashMax = 128;
 constexpr int64_t kWaveStreamMax = 1 << 16;
 struct ItemLists {
     DBuf<Item> block, wave;
