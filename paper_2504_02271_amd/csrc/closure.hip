@@ -819,7 +819,13 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
         // an owner-centric partner meets every chunk of its owner.
         if (PER_WEDGE || PER_EDGE) {
             const bool seg_direct = MID ? whole_chunk : single;
-            const bool ent_direct = MID ? (whole_in && (int64_t)r < A.kdirect_end) : single;
+            if (MID && PER_EDGE) {
+                // the middle's j-role total of this item: one atomic per wave
+                unsigned long long sj = tid < nseg ? (unsigned long long)seg_cjm[tid] : 0ull;
+#pragma unroll
+                for (int o = kWave / 2; o > 0; o >>= 1) sj += __shfl_xor(sj, o, kWave);
+                if (lane == 0 && sj) atomicAdd(&A.tedge[r], sj);
+            }
             if (tid < nseg) {
                 const int64_t e = MID ? my_wedge : base + item.jb + tid;
                 if (seg_direct) {
@@ -833,8 +839,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
             if (PER_EDGE) {
                 for (int qq = tid; qq < cl; qq += kBlock) {
                     const int64_t e = base + item.cb + qq;
-                    if (ent_direct) A.cwkm[e] = ent_ck[qq];
-                    else if (ent_ck[qq]) atomicAdd(&A.cwkm[e], ent_ck[qq]);
+                    if (MID) {
+                        if (ent_ck[qq])
+                            atomicAdd(&A.tedge[gld(G.fadj + e) >> wbits], (unsigned long long)ent_ck[qq]);
+                    } else if (single) {
+                        A.cwkm[e] = ent_ck[qq];
+                    } else if (ent_ck[qq]) {
+                        atomicAdd(&A.cwkm[e], ent_ck[qq]);
+                    }
                 }
             }
         }
@@ -1027,10 +1039,17 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                 if (PER_WEDGE) A.cwj[e] = Wl.cj[lane];
                 if (PER_EDGE) A.cwjm[e] = Wl.cjm[lane];
             }
+            if (MID && PER_EDGE) {
+                unsigned long long sj = Wl.cjm[lane];   // 0 beyond the item's partners
+#pragma unroll
+                for (int o = kWave / 2; o > 0; o >>= 1) sj += __shfl_xor(sj, o, kWave);
+                if (lane == 0 && sj) atomicAdd(&A.tedge[r], sj);
+            }
             if (PER_EDGE)
                 for (int t = lane; t < d; t += kWave) {
-                    if (!MID || (int64_t)r < A.kdirect_end) A.cwkm[base + t] = Wl.ent_ck[t];
-                    else if (Wl.ent_ck[t]) atomicAdd(&A.cwkm[base + t], Wl.ent_ck[t]);
+                    if (!MID) A.cwkm[base + t] = Wl.ent_ck[t];
+                    else if (Wl.ent_ck[t])
+                        atomicAdd(&A.tedge[Wl.ent[t] >> wbits], (unsigned long long)Wl.ent_ck[t]);
                 }
         }
     }
@@ -1136,10 +1155,12 @@ __global__ void k_stream_size(const int64_t *fptr, const uint32_t *fadj, int64_t
 }
 
 // per-hyperedge counts from the per-wedge role counters: the j- and k-role
-// counts of hyperwedge (r, x) go to x (one thread per hyperwedge) ...
-__global__ void k_edge_counts_roles(const uint32_t *fadj, int64_t nw, int wbits, const uint32_t *cwjm,
+// counts of hyperwedge (r, x), e0 <= position < nw, go to x (one thread per
+// hyperwedge) ...
+__global__ void k_edge_counts_roles(const uint32_t *fadj, int64_t e0, int64_t nw, int wbits, const uint32_t *cwjm,
                                     const uint32_t *cwkm, unsigned long long *t) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nw; e += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t e = e0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nw;
+         e += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t c = cwjm[e] + cwkm[e];
         if (c) atomicAdd(&t[fadj[e] >> wbits], (unsigned long long)c);
     }
@@ -2250,9 +2271,11 @@ void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21],
     // probing direction: around the middle hyperedge unless asked otherwise
     // or its in-list does not fit (then around the owner)
     bool mid = !(flags & HTRI_COUNT_OWNER_PROBE) && owner_end > 0;
+    int64_t mid_wedges = 0;   // hyperwedges of the owners before owner_end (the in-list)
     if (mid) {
         size_t free_b = 0, total_b = 0;
         const int64_t n_in = read_i64(g.fptr.p + owner_end, s);
+        mid_wedges = n_in;
         if (n_in >= (int64_t)UINT32_MAX) mid = false;
         else if (hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
                  (double)inlist_bytes(g, owner_end) > 0.9 * (double)free_b)
@@ -2292,11 +2315,18 @@ void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21],
     const bool pe = t_dev != nullptr;
     const bool pw = cw_dev != nullptr;
     DBuf<uint32_t> cwjm, cwkm;
+    // per-hyperedge totals by rank; middle-centric items add to them during
+    // the closure, and the role reduce adds the hyperwedges from e_roles on
+    // (the window's, or all of them when probing around the owner)
+    DBuf<unsigned long long> tsum;
+    const int64_t e_roles = mid ? mid_wedges : 0;
     if (pe) {
         cwjm.alloc(A, g.nw);
         cwkm.alloc(A, g.nw);
+        tsum.alloc(A, m);
         fill_u32(cwjm.p, g.nw, 0, s);
         fill_u32(cwkm.p, g.nw, 0, s);
+        fill_u64((uint64_t *)tsum.p, m, 0, s);
     }
     if (pw) fill_u32(cw_dev, g.nw, 0, s);
 
@@ -2321,19 +2351,18 @@ void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21],
     a.counts = ctr.p + 1;
     a.probes = ctr.p + 22;
     a.staged = ctr.p + 28;
-    a.kdirect_end = owner_end;
+    a.tedge = mid && pe ? tsum.p : nullptr;
     close_window(g, win, mask, lut.p, ctr.p + 1, ctr.p + 26, cw_dev, pe ? cwjm.p : nullptr, pe ? cwkm.p : nullptr);
     HTRI_HIP(hipEventRecord(ew, s));
     launch_close_kernel(cfg, pe, pw, a, nblocks, s, mid);
     HTRI_HIP(hipEventRecord(e2, s));
 
     if (pe) {
-        DBuf<unsigned long long> t(A, m);
-        fill_u64((uint64_t *)t.p, m, 0, s);
+        DBuf<unsigned long long> &t = tsum;
         if (m > 0) {
-            if (g.nw > 0) {
-                hipLaunchKernelGGL(k_edge_counts_roles, dim3(grid_for(g.nw, 256, 16384)), dim3(256), 0, s, g.fadj.p,
-                                   g.nw, g.wbits, cwjm.p, cwkm.p, t.p);
+            if (g.nw > e_roles) {
+                hipLaunchKernelGGL(k_edge_counts_roles, dim3(grid_for(g.nw - e_roles, 256, 16384)), dim3(256), 0, s,
+                                   g.fadj.p, e_roles, g.nw, g.wbits, cwjm.p, cwkm.p, t.p);
                 HTRI_LAUNCH_CHECK();
             }
             hipLaunchKernelGGL(k_edge_counts_owner, dim3(grid_for(m * kWave, 256, 8192)), dim3(256), 0, s, g.fptr.p, m,

@@ -240,8 +240,9 @@ struct CloseArgs {
     unsigned long long *counts;     // [graphs][21]; [g][0] unused (total formed on the host)
     unsigned long long *probes;     // entries probed
     unsigned long long *staged;     // hashed entries staged (null: not counted)
-    int64_t kdirect_end;            // middle-centric: middles >= this add k-role counts atomically
-                                    // (the dense window has written those hyperwedges' counters)
+    unsigned long long *tedge;      // middle-centric with per-edge counts: per-hyperedge totals by
+                                    // rank, to which each item adds its middle's j-role counts and
+                                    // its hashed entries' k-role counts (cwkm is left to the window)
 };
 // Owners with at most kWaveOwnerMax forward entries whose partner lists hold
 // at most kWaveStreamMax entries in total are closed by one wave each.
