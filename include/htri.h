@@ -91,6 +91,10 @@ typedef struct {
 #define HTRI_INPUT_ON_DEVICE 2u   /* offsets/members are device pointers      */
 #define HTRI_OUTPUT_ON_DEVICE 4u  /* per_edge / per_wedge are device pointers */
 #define HTRI_ORDER_INPUT 8u       /* orient by normalised id, not by delta    */
+/* Hyperwedge build with 64-bit sort keys in its LDS tiles, the form graphs
+ * of 2^24 or more hyperedges need (smaller graphs use 32-bit keys); the
+ * hyperwedges are the same either way. */
+#define HTRI_WIDE_TILE_KEYS 256u
 /* htri_count_patterns flags (with HTRI_OUTPUT_ON_DEVICE) */
 #define HTRI_COUNT_NO_WINDOW 16u     /* close every owner by probing           */
 #define HTRI_COUNT_WINDOW_ALWAYS 32u /* use the dense window whenever it holds */

@@ -75,7 +75,7 @@ htri_status htri_graph_load(const int64_t *edge_offsets, int64_t num_edges, cons
         g_load_err = "null pointer or negative size";
         return HTRI_E_INVALID;
     }
-    if (flags & ~(HTRI_DEDUPE_EDGES | HTRI_INPUT_ON_DEVICE | HTRI_ORDER_INPUT)) {
+    if (flags & ~(HTRI_DEDUPE_EDGES | HTRI_INPUT_ON_DEVICE | HTRI_ORDER_INPUT | HTRI_WIDE_TILE_KEYS)) {
         std::lock_guard<std::mutex> lk(g_err_mu);
         g_load_err = "unknown flag";
         return HTRI_E_INVALID;

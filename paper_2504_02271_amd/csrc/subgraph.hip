@@ -139,7 +139,8 @@ void subgraph_select(Graph &g, double sigma, uint64_t seed, int mode, Graph &out
     HTRI_HIP(hipStreamSynchronize(s));
     // the kept hyperedges are distinct sets already; their order is the
     // subgraph's input order
-    const uint32_t flags = HTRI_DEDUPE_EDGES | HTRI_INPUT_ON_DEVICE | (g.flags & HTRI_ORDER_INPUT);
+    const uint32_t flags =
+        HTRI_DEDUPE_EDGES | HTRI_INPUT_ON_DEVICE | (g.flags & (HTRI_ORDER_INPUT | HTRI_WIDE_TILE_KEYS));
     graph_load(out, new_off.p, n, new_mem.p, g.n, flags);
 }
 

@@ -20,6 +20,7 @@ HTRI_DEDUPE_EDGES = 1
 HTRI_INPUT_ON_DEVICE = 2
 HTRI_OUTPUT_ON_DEVICE = 4
 HTRI_ORDER_INPUT = 8
+HTRI_WIDE_TILE_KEYS = 256
 HTRI_COUNT_NO_WINDOW = 16
 HTRI_COUNT_WINDOW_ALWAYS = 32
 HTRI_COUNT_INCLUSION_CLASSES = 64

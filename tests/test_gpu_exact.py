@@ -269,6 +269,27 @@ def test_coauthorship_workload(htri):
     assert np.array_equal(c2, c3) and np.array_equal(pe2, pe3) and np.array_equal(pw2, pw3)
 
 
+def test_wide_tile_keys(htri):
+    """The 64-bit tile keys (the form graphs of 2^24 or more hyperedges take)
+    against the oracle, and the same hyperwedges as the 32-bit keys on the
+    co-authorship workload."""
+    wide = htri.HTRI_DEDUPE_EDGES | htri.HTRI_WIDE_TILE_KEYS
+    check_exact(htri, synth.generate(synth.config("tiny")), flags=wide)
+    check_exact(htri, synth.generate(synth.config("tiny")), flags=wide | htri.HTRI_ORDER_INPUT)
+    g = synth.generate(synth.config("coauth"))
+    res = []
+    for flags in (htri.HTRI_DEDUPE_EDGES, wide):
+        G = htri.graph_load(g.offsets, g.members, g.num_vertices, flags=flags)
+        s = G.build_wedges()
+        src, dst, om = G.get_wedges()
+        res.append((s, src, dst, om, G.count_patterns(per_edge=True)[:2]))
+        G.close()
+    (s0, a0, b0, w0, (c0, t0)), (s1, a1, b1, w1, (c1, t1)) = res
+    assert np.array_equal(s0, s1)
+    assert np.array_equal(a0, a1) and np.array_equal(b0, b1) and np.array_equal(w0, w1)
+    assert np.array_equal(c0, c1) and np.array_equal(t0, t1)
+
+
 def test_owner_with_many_incidences(htri):
     """An owner meeting more incidences than an LDS tile holds goes through
     the global sort: hyperedge 0 (3,000 vertices, no stored mask) owns its
