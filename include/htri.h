@@ -112,7 +112,8 @@ typedef struct {
  *                 hyperedge x holds members[edge_offsets[x] .. edge_offsets[x+1]).
  *   members       int32[edge_offsets[num_edges]], ids in [0, num_vertices);
  *                 any order; a repeated id inside one hyperedge counts once.
- *   flags         HTRI_DEDUPE_EDGES | HTRI_INPUT_ON_DEVICE | HTRI_ORDER_INPUT.
+ *   flags         HTRI_DEDUPE_EDGES | HTRI_INPUT_ON_DEVICE | HTRI_ORDER_INPUT |
+ *                 HTRI_WIDE_TILE_KEYS (kept for htri_build_wedges).
  *   alloc         NULL or an allocator used for every device buffer.
  *   stream        hipStream_t (NULL = default stream).
  *   out           receives the handle; caller frees it with htri_graph_free.
