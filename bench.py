@@ -370,6 +370,14 @@ def main() -> int:
             "entries_probed": int(cstats[1]),
             "in_list_hyperwedges": int(cstats[13]),
             "hashed_entries_staged": int(cstats[15]),
+            # the whole step against the method's own byte count: 5 B per
+            # hyperwedge plus 5 B per entry of the owner-centric probe stream
+            # S, the stream a plain two-step closure reads
+            "step_vs_owner_centric_stream": {
+                "bytes": 5 * (nw + int(cstats[0])),
+                "GBps_equivalent": 5 * (nw + int(cstats[0])) / (ms_per_step / 1e3) / 1e9,
+                "frac_equivalent": 5 * (nw + int(cstats[0])) / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS,
+            },
         },
         "window": {
             "kernels": "k_window_rows + k_close_window (owners of the top ranks, bitmap intersection)",
