@@ -33,6 +33,27 @@ def test_library_exports_every_declared_function():
     assert not missing, missing
 
 
+def test_binding_constants_match_the_header():
+    """Every HTRI_* constant the binding defines has the header's value, and
+    the header's flag bits of one function do not collide."""
+    from paper_2504_02271_amd import htri
+    text = open(HEADER).read()
+    defs = {k: int(v) for k, v in re.findall(r"#define\s+(HTRI_[A-Z0-9_]+)\s+(\d+)u?\b", text)}
+    consts = {k: v for k, v in vars(htri).items() if re.fullmatch(r"HTRI_[A-Z0-9_]+", k) and isinstance(v, int)}
+    assert len(consts) >= 10
+    for k, v in consts.items():
+        if k in defs:
+            assert defs[k] == v, (k, defs[k], v)
+        else:
+            assert k == "HTRI_OK", k               # an enum value, not a #define
+    load = [defs[k] for k in ("HTRI_DEDUPE_EDGES", "HTRI_INPUT_ON_DEVICE", "HTRI_OUTPUT_ON_DEVICE",
+                              "HTRI_ORDER_INPUT", "HTRI_WIDE_TILE_KEYS")]
+    count = [defs[k] for k in ("HTRI_OUTPUT_ON_DEVICE", "HTRI_COUNT_NO_WINDOW", "HTRI_COUNT_WINDOW_ALWAYS",
+                               "HTRI_COUNT_INCLUSION_CLASSES", "HTRI_COUNT_OWNER_PROBE")]
+    for bits in (load, count):
+        assert all(b & (b - 1) == 0 for b in bits) and len(set(bits)) == len(bits)   # distinct single bits
+
+
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     from paper_2504_02271_amd import htri
     monkeypatch.setattr(htri, "LIB_PATH", str(tmp_path / "missing.so"))
