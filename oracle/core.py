@@ -63,6 +63,8 @@ def _load():
     lib.orc_get_degrees.argtypes = [P, P]
     lib.orc_count.argtypes = [P, ctypes.c_int, u32, P, P, P]
     lib.orc_count.restype = ctypes.c_int
+    lib.orc_count_range.argtypes = [P, i64, i64, ctypes.c_int, u32, P, P, P]
+    lib.orc_count_range.restype = ctypes.c_int
     lib.orc_wedge_closure.argtypes = [P, P, P, i64, P]
     lib.orc_wedge_closure.restype = ctypes.c_int
     lib.orc_build_vertex_lists.argtypes = [P]
@@ -175,6 +177,21 @@ class OracleGraph:
         if rc != ORC_OK:
             raise OracleError(rc, "count")
         return CountResult(H, t, cw)
+
+    def count_range(self, i0: int, i1: int, nthreads: int = 0, edge_mask: int = 0x1FFFFE,
+                    per_edge: bool = True) -> CountResult:
+        """The count restricted to owners [i0, i1) (triangles whose smallest
+        id lies there); results over ranges tiling [0, m) sum to count()."""
+        self.build_wedges()
+        if nthreads <= 0:
+            nthreads = max(1, min(16, os.cpu_count() or 1))
+        H = np.zeros(21, np.int64)
+        t = np.zeros(self.m, np.int64) if per_edge else None
+        rc = self._lib.orc_count_range(self._h, int(i0), int(i1), int(nthreads),
+                                       ctypes.c_uint32(edge_mask), _ptr(H), _ptr(t), None)
+        if rc != ORC_OK:
+            raise OracleError(rc, "count_range")
+        return CountResult(H, t, None)
 
     def wedge_closure(self, wi: np.ndarray, wj: np.ndarray) -> np.ndarray:
         """int64[n, 21] per-pattern forward closure of the given wedges (i<j)."""

@@ -392,6 +392,7 @@ int orc_classify(int64_t si, int64_t sj, int64_t sk, int64_t wij, int64_t wik, i
 typedef struct {
     orc_graph *g;
     atomic_llong next;
+    int64_t end;               /* owners [next at start, end) are counted */
     int nthreads;
     uint32_t edge_mask;        /* bit p: count pattern p into per-edge counts */
     int64_t *H;                /* nthreads x 21 */
@@ -410,8 +411,8 @@ static void *count_worker(void *p) {
     const int64_t chunk = 64;
     for (;;) {
         int64_t i0 = atomic_fetch_add(&job->next, chunk);
-        if (i0 >= g->m) break;
-        int64_t i1 = i0 + chunk < g->m ? i0 + chunk : g->m;
+        if (i0 >= job->end) break;
+        int64_t i1 = i0 + chunk < job->end ? i0 + chunk : job->end;
         for (int64_t i = i0; i < i1; i++) {
             int64_t si = esize(g, i);
             for (int64_t q = g->wptr[i]; q < g->wptr[i + 1]; q++) {
@@ -441,18 +442,20 @@ static void *count_worker(void *p) {
     return NULL;
 }
 
-/* Exact count of every pattern.  H[0] = total, H[p] for p = 1..20.
- * t (may be NULL): per-hyperedge count of the triangles whose pattern bit is
- * set in edge_mask.  cw (may be NULL): per-wedge forward closure count in the
- * wedge order of orc_get_wedges. */
-int orc_count(void *h, int nthreads, uint32_t edge_mask, int64_t H_out[21], int64_t *t_out,
-              int32_t *cw_out) {
+/* The count below restricted to the owners i in [i0, i1): every hyper-
+ * triangle whose smallest id lies in the range, counted exactly as the full
+ * count does.  Summing the results over ranges that tile [0, m) gives the
+ * full count's H and t (each triangle is met at its smallest id only). */
+int orc_count_range(void *h, int64_t i0, int64_t i1, int nthreads, uint32_t edge_mask,
+                    int64_t H_out[21], int64_t *t_out, int32_t *cw_out) {
     orc_graph *g = h;
     if (!g->have_wedges) return ORC_E_STATE;
+    if (i0 < 0 || i1 < i0 || i1 > g->m) return ORC_E_INVALID;
     if (nthreads < 1) nthreads = 1;
     count_job job;
     job.g = g;
-    atomic_init(&job.next, 0);
+    atomic_init(&job.next, i0);
+    job.end = i1;
     job.nthreads = nthreads;
     job.edge_mask = edge_mask;
     job.H = calloc((size_t)nthreads * 21, sizeof(int64_t));
@@ -477,6 +480,16 @@ int orc_count(void *h, int nthreads, uint32_t edge_mask, int64_t H_out[21], int6
     }
     free(job.H); free(job.t); free(th); free(args);
     return ORC_OK;
+}
+
+/* Exact count of every pattern.  H[0] = total, H[p] for p = 1..20.
+ * t (may be NULL): per-hyperedge count of the triangles whose pattern bit is
+ * set in edge_mask.  cw (may be NULL): per-wedge forward closure count in the
+ * wedge order of orc_get_wedges. */
+int orc_count(void *h, int nthreads, uint32_t edge_mask, int64_t H_out[21], int64_t *t_out,
+              int32_t *cw_out) {
+    orc_graph *g = h;
+    return orc_count_range(h, 0, g->m, nthreads, edge_mask, H_out, t_out, cw_out);
 }
 
 /* ------------------------------------------------ on-demand neighbourhoods
