@@ -258,16 +258,34 @@ typedef struct {
     int32_t flags;            /* HTRI_SAMPLE_EXACT_INCLUSION or 0              */
     const htri_model *model;  /* required for proposal 1                       */
     double defensive_mix;     /* lambda: q = (1-lambda) q_model + lambda/|pool| */
+                              /* (proposal 1 needs lambda > 0: the network's   */
+                              /* score can be 0, and unbiasedness needs q > 0  */
+                              /* on every hyperwedge; lambda <= 0 is refused)  */
     double pool_factor;       /* learned: candidate pool = pool_factor*samples  */
                               /* (<= 0: the pool is every wedge)                */
 } htri_sample_params;
 
 /* Hyperwedge-sampling estimate (Algorithm 6, sigma = 1; unbiased by Lemma
  * 4.1, and for any positive proposal by importance weighting).
+ *   proposal 0 (uniform): n draws w_t = floor(u_t * |wedges| / 2^64) with u_t
+ *     the 64-bit word t of Philox stream 0 under `seed`;
+ *     est_p = (|wedges| / n) * sum_t c_p(w_t), c_p(w) = the third hyperedges
+ *     after w's later end that close w in pattern p.
+ *   proposal 1 (learned): a pool of P = round(pool_factor * n) hyperwedges
+ *     drawn uniformly (Philox stream 1; every hyperwedge when pool_factor <=
+ *     0, P = |wedges|), scored s_u (htri_proposal_scores), the float64 CDF
+ *     C_u = (1 - lambda) * S_u / S_P + lambda * (u + 1) / P over the inclusive
+ *     sums S_u of the scores; draw t takes the first u with C_u > U_t * C_P,
+ *     U_t = (word t of Philox stream 2 >> 11) * 2^-53, with the realised
+ *     probability q_u = (C_u - C_{u-1}) / C_P, and
+ *     est_p = (|wedges| / P) * (1/n) * sum_t c_p(pool[u_t]) / q_{u_t}.
+ *   With HTRI_SAMPLE_EXACT_INCLUSION, drawn inclusion hyperwedges close
+ *   nothing and the exact closures of all inclusion hyperwedges are added.
  *   est       double[21] host array: estimated H, [0] = total.
  *   stderr_   NULL or double[21]: standard error of each estimate.
  *   time_ms   NULL or double: device time of the estimate.
- * Errors: HTRI_E_STATE, HTRI_E_INVALID, HTRI_E_OOM, HTRI_E_DEVICE. */
+ * Errors: HTRI_E_STATE, HTRI_E_INVALID (also lambda outside [0, 1], or
+ * lambda <= 0 with proposal 1), HTRI_E_OOM, HTRI_E_DEVICE. */
 htri_status htri_estimate(htri_graph *g, const htri_sample_params *p, double est[21],
                           double stderr_[21], double *time_ms);
 
@@ -301,6 +319,16 @@ htri_status htri_subgraph(htri_graph *g, double sigma, uint64_t seed, int32_t mo
  * [0] total, [p] pattern p).  The sampling kernels' closure step. */
 htri_status htri_close_wedges(htri_graph *g, const int64_t *wedge_idx, int64_t n, int64_t *out);
 
+/* The learned proposal's score of listed hyperwedges (the s_u of
+ * htri_estimate): expm1(min(max(f(x_w), 0), 30)) with f the network and x_w
+ * the 16 features of hyperwedge w, computed in float32 and returned as
+ * float64.  wedge_idx: host int64[n] indices in the htri_get_wedges order,
+ * or NULL with n = |wedges| for every hyperwedge; out: host double[n].
+ * Errors: HTRI_E_INVALID (index out of range, NULL), HTRI_E_STATE,
+ * HTRI_E_OOM, HTRI_E_DEVICE. */
+htri_status htri_proposal_scores(htri_graph *g, const htri_model *model, const int64_t *wedge_idx, int64_t n,
+                                 double *out);
+
 /* Per-wedge proposal features (16 float32 per wedge, htri_get_wedges order)
  * into a device array float[|wedges|*16]. */
 htri_status htri_wedge_features(htri_graph *g, float *dev_features);
@@ -313,6 +341,17 @@ htri_status htri_model_create(uint64_t seed, void *stream, htri_model **out);
 void htri_model_free(htri_model *m);
 htri_status htri_model_get_params(const htri_model *m, float *host_params);
 htri_status htri_model_set_params(htri_model *m, const float *host_params);
+/* Save the parameters as raw float32 (little endian, the layout above,
+ * 21,252 bytes) at `path`, and their description as JSON at `path`.json
+ * (format "htri-proposal-mlp", layers, dtype, num_params, layout).  Load
+ * reads both back: the JSON must name this network and the raw file hold
+ * exactly 5313 finite float32 values; the Adam state is reset as by
+ * htri_model_set_params.  Errors: HTRI_E_INVALID (NULL, I/O failure,
+ * mismatched file; htri_model_last_error says which), HTRI_E_DEVICE. */
+htri_status htri_model_save(const htri_model *m, const char *path);
+htri_status htri_model_load(htri_model *m, const char *path);
+/* Message of the last failure on m. */
+const char *htri_model_last_error(const htri_model *m);
 /* Forward over n feature rows (device arrays): out[n] = network output. */
 htri_status htri_model_forward(const htri_model *m, const float *dev_x, int64_t n, float *dev_out);
 /* Mean-squared-error loss 0.5*mean((f(x)-y)^2) and its gradient with

@@ -58,6 +58,8 @@ def _load():
     lib.orc_get_csr.argtypes = [P, P, P, P]
     lib.orc_build_wedges.argtypes = [P]
     lib.orc_build_wedges.restype = ctypes.c_int
+    lib.orc_build_wedges_threads.argtypes = [P, ctypes.c_int]
+    lib.orc_build_wedges_threads.restype = ctypes.c_int
     lib.orc_summary.argtypes = [P, P]
     lib.orc_get_wedges.argtypes = [P, P, P, P]
     lib.orc_get_degrees.argtypes = [P, P]
@@ -134,9 +136,11 @@ class OracleGraph:
         return off, mem, orig
 
     # -- step 1 ---------------------------------------------------------
-    def build_wedges(self) -> None:
+    def build_wedges(self, nthreads: int = 1) -> None:
+        """Step 1; owners are split over nthreads threads (same result for
+        any count)."""
         if not self._wedges_built:
-            rc = self._lib.orc_build_wedges(self._h)
+            rc = self._lib.orc_build_wedges_threads(self._h, int(max(1, nthreads)))
             if rc != ORC_OK:
                 raise OracleError(rc, "build_wedges")
             self._wedges_built = True

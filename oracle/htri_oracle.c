@@ -202,21 +202,33 @@ int orc_build_vertex_lists(void *h);
 /* Step 1 (Algorithm 2).  E_v lists ascending by hyperedge id; for every e_i
  * the partners j > i with omega_ij, found by counting, for each v in e_i,
  * the hyperedges of E_v after e_i (the same multiset Algorithm 2's merge
- * over the E_v lists walks).  Also the symmetric adjacency N(x). */
-int orc_build_wedges(void *h) {
-    orc_graph *g = h;
-    if (g->have_wedges) return ORC_OK;
-    int64_t m = g->m;
-    int rc0 = orc_build_vertex_lists(h);
-    if (rc0 != ORC_OK) return rc0;
+ * over the E_v lists walks).  Also the symmetric adjacency N(x).
+ *
+ * Owners are independent (the paper's Par-adv runs step 1 with threads over
+ * hyperedges): a count pass gives each owner's number of partners, a prefix
+ * sum their offsets, and a fill pass writes each owner's sorted partners at
+ * its offset.  Threads claim owners in chunks; every owner's output depends
+ * on that owner alone, so the result is the same for any thread count. */
+typedef struct {
+    orc_graph *g;
+    int pass;                  /* 0: count partners, 1: fill them */
+    atomic_llong next;
+    atomic_int err;
+} wedge_job;
 
-    /* count pass then fill pass, each with a dense counter + touched list */
+static void *wedge_worker(void *p) {
+    wedge_job *job = p;
+    orc_graph *g = job->g;
+    int64_t m = g->m;
     int32_t *cnt = calloc((size_t)(m ? m : 1), sizeof(int32_t));
     int32_t *touched = malloc(sizeof(int32_t) * (m ? m : 1));
-    g->wptr = calloc((size_t)m + 1, sizeof(int64_t));
-    if (!cnt || !touched || !g->wptr) { free(cnt); free(touched); return ORC_E_OOM; }
-    for (int pass = 0; pass < 2; pass++) {
-        for (int64_t i = 0; i < m; i++) {
+    if (!cnt || !touched) { free(cnt); free(touched); atomic_store(&job->err, ORC_E_OOM); return NULL; }
+    const int64_t chunk = 256;
+    for (;;) {
+        int64_t i0 = atomic_fetch_add(&job->next, chunk);
+        if (i0 >= m) break;
+        int64_t i1 = i0 + chunk < m ? i0 + chunk : m;
+        for (int64_t i = i0; i < i1; i++) {
             int64_t nt = 0;
             for (int64_t t = g->off[i]; t < g->off[i + 1]; t++) {
                 int32_t v = g->mem[t];
@@ -226,7 +238,7 @@ int orc_build_wedges(void *h) {
                     if (cnt[j]++ == 0) touched[nt++] = j;
                 }
             }
-            if (pass == 0) {
+            if (job->pass == 0) {
                 g->wptr[i + 1] = nt;
             } else {
                 qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);
@@ -238,15 +250,44 @@ int orc_build_wedges(void *h) {
             }
             for (int64_t q = 0; q < nt; q++) cnt[touched[q]] = 0;
         }
-        if (pass == 0) {
-            for (int64_t i = 0; i < m; i++) g->wptr[i + 1] += g->wptr[i];
-            g->nw = g->wptr[m];
-            g->wj = malloc(sizeof(int32_t) * (g->nw ? g->nw : 1));
-            g->wom = malloc(sizeof(int32_t) * (g->nw ? g->nw : 1));
-            if (!g->wj || !g->wom) { free(cnt); free(touched); return ORC_E_OOM; }
-        }
     }
     free(cnt); free(touched);
+    return NULL;
+}
+
+static int run_wedge_pass(orc_graph *g, int pass, int nthreads) {
+    wedge_job job;
+    job.g = g;
+    job.pass = pass;
+    atomic_init(&job.next, 0);
+    atomic_init(&job.err, ORC_OK);
+    pthread_t *th = malloc(sizeof(pthread_t) * nthreads);
+    if (!th) return ORC_E_OOM;
+    for (int q = 0; q < nthreads; q++) pthread_create(&th[q], NULL, wedge_worker, &job);
+    for (int q = 0; q < nthreads; q++) pthread_join(th[q], NULL);
+    free(th);
+    return atomic_load(&job.err);
+}
+
+int orc_build_wedges_threads(void *h, int nthreads) {
+    orc_graph *g = h;
+    if (g->have_wedges) return ORC_OK;
+    if (nthreads < 1) nthreads = 1;
+    int64_t m = g->m;
+    int rc0 = orc_build_vertex_lists(h);
+    if (rc0 != ORC_OK) return rc0;
+
+    g->wptr = calloc((size_t)m + 1, sizeof(int64_t));
+    if (!g->wptr) return ORC_E_OOM;
+    int rc = run_wedge_pass(g, 0, nthreads);
+    if (rc != ORC_OK) return rc;
+    for (int64_t i = 0; i < m; i++) g->wptr[i + 1] += g->wptr[i];
+    g->nw = g->wptr[m];
+    g->wj = malloc(sizeof(int32_t) * (g->nw ? g->nw : 1));
+    g->wom = malloc(sizeof(int32_t) * (g->nw ? g->nw : 1));
+    if (!g->wj || !g->wom) return ORC_E_OOM;
+    rc = run_wedge_pass(g, 1, nthreads);
+    if (rc != ORC_OK) return rc;
 
     /* types (Def. 2.3, Algorithm 2's final test) */
     g->n_incl = g->n_inter = 0;
@@ -280,6 +321,8 @@ int orc_build_wedges(void *h) {
     g->have_wedges = 1;
     return ORC_OK;
 }
+
+int orc_build_wedges(void *h) { return orc_build_wedges_threads(h, 1); }
 
 int64_t orc_num_wedges(void *h) { return ((orc_graph *)h)->nw; }
 
@@ -392,6 +435,7 @@ int orc_classify(int64_t si, int64_t sj, int64_t sk, int64_t wij, int64_t wik, i
 typedef struct {
     orc_graph *g;
     atomic_llong next;
+    atomic_int err;
     int64_t end;               /* owners [next at start, end) are counted */
     int nthreads;
     uint32_t edge_mask;        /* bit p: count pattern p into per-edge counts */
@@ -402,12 +446,42 @@ typedef struct {
 
 typedef struct { count_job *job; int tid; } count_arg;
 
+/* the sorted common vertices of e_i and e_j (Omega_ij of Def. 2.2) */
+static int64_t common_vertices(const orc_graph *g, int64_t i, int64_t j, int32_t *out) {
+    const int32_t *a = g->mem + g->off[i], *ae = g->mem + g->off[i + 1];
+    const int32_t *b = g->mem + g->off[j], *be = g->mem + g->off[j + 1];
+    int64_t n = 0;
+    while (a < ae && b < be) {
+        if (*a < *b) a++;
+        else if (*b < *a) b++;
+        else { out[n++] = *a; a++; b++; }
+    }
+    return n;
+}
+
+/* |Omega & e_k| for a sorted vertex list Omega, by a merge with e_k; with
+ * Omega = e_i & e_j this is g = |e_i & e_j & e_k| */
+static int64_t common_with(const orc_graph *g, const int32_t *om, int64_t n, int64_t k) {
+    const int32_t *c = g->mem + g->off[k], *ce = g->mem + g->off[k + 1];
+    int64_t q = 0, r = 0;
+    while (q < n && c < ce) {
+        if (om[q] < *c) q++;
+        else if (*c < om[q]) c++;
+        else { r++; q++; c++; }
+    }
+    return r;
+}
+
 static void *count_worker(void *p) {
     count_arg *arg = p;
     count_job *job = arg->job;
     orc_graph *g = job->g;
     int64_t *H = job->H + 21 * arg->tid;
     int64_t *t = job->t ? job->t + g->m * arg->tid : NULL;
+    int64_t maxs = 1;
+    for (int64_t x = 0; x < g->m; x++) if (esize(g, x) > maxs) maxs = esize(g, x);
+    int32_t *om = malloc(sizeof(int32_t) * (size_t)maxs);
+    if (!om) { atomic_store(&job->err, ORC_E_OOM); return NULL; }
     const int64_t chunk = 64;
     for (;;) {
         int64_t i0 = atomic_fetch_add(&job->next, chunk);
@@ -418,6 +492,7 @@ static void *count_worker(void *p) {
             for (int64_t q = g->wptr[i]; q < g->wptr[i + 1]; q++) {
                 int64_t j = g->wj[q], wij = g->wom[q], sj = esize(g, j);
                 int32_t closed = 0;
+                int64_t nom = common_vertices(g, i, j, om);   /* Omega_ij, nom == wij */
                 /* merge N(i) and N(j), keeping k > j */
                 int64_t a = g->nptr[i], ae = g->nptr[i + 1];
                 int64_t b = g->nptr[j], be = g->nptr[j + 1];
@@ -428,7 +503,7 @@ static void *count_worker(void *p) {
                     if (g->nadj[a] > g->nadj[b]) { b++; continue; }
                     int64_t k = g->nadj[a];
                     int64_t wik = g->nom[a], wjk = g->nom[b];
-                    int64_t gg = triple_common(g, i, j, k);
+                    int64_t gg = common_with(g, om, nom, k);
                     int p = classify(si, sj, esize(g, k), wij, wik, wjk, gg);
                     H[p]++;
                     closed++;
@@ -439,6 +514,7 @@ static void *count_worker(void *p) {
             }
         }
     }
+    free(om);
     return NULL;
 }
 
@@ -455,6 +531,7 @@ int orc_count_range(void *h, int64_t i0, int64_t i1, int nthreads, uint32_t edge
     count_job job;
     job.g = g;
     atomic_init(&job.next, i0);
+    atomic_init(&job.err, ORC_OK);
     job.end = i1;
     job.nthreads = nthreads;
     job.edge_mask = edge_mask;
@@ -469,6 +546,10 @@ int orc_count_range(void *h, int64_t i0, int64_t i1, int nthreads, uint32_t edge
         pthread_create(&th[q], NULL, count_worker, &args[q]);
     }
     for (int q = 0; q < nthreads; q++) pthread_join(th[q], NULL);
+    if (atomic_load(&job.err) != ORC_OK) {
+        free(job.H); free(job.t); free(th); free(args);
+        return atomic_load(&job.err);
+    }
     memset(H_out, 0, 21 * sizeof(int64_t));
     for (int q = 0; q < nthreads; q++)
         for (int p = 1; p <= 20; p++) H_out[p] += job.H[21 * q + p];

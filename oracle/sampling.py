@@ -91,6 +91,45 @@ def uniform_estimate(closures: np.ndarray, num_wedges: int):
     return est, se
 
 
+def learned_cdf(scores: np.ndarray, lam: float) -> np.ndarray:
+    """Mixed proposal CDF over a pool of P candidates: the inclusive float64
+    sums S of the scores, C_u = (1 - lam) / S_P * S_u + lam / P * (u + 1)
+    (uniform, (u + 1) / P, when every score is 0)."""
+    P = scores.shape[0]
+    S = np.cumsum(np.asarray(scores, np.float64))
+    tot = S[-1]
+    if tot > 0:
+        return ((1.0 - lam) / tot) * S + (lam / P) * np.arange(1, P + 1, dtype=np.float64)
+    return (1.0 / P) * np.arange(1, P + 1, dtype=np.float64)
+
+
+def learned_estimate(scores: np.ndarray, pool: np.ndarray, num_wedges: int, lam: float, seed: int, n: int,
+                     close):
+    """Importance-sampling estimate with a learned proposal over a pool
+    (Hansen-Hurwitz with replacement, each closure divided by its realised
+    draw probability; the pool's uniform estimate scaled by |wedges| / P).
+
+    scores: float64[P] the proposal's scores of the pool members; pool:
+    int64[P] their wedge indices; close(idx) -> int64[n, 21] the forward
+    closures of the listed wedges.  Draw t is the first u with
+    C_u > U_t * C_P, U_t the t-th double of Philox stream 2; its probability
+    is q_u = (C_u - C_{u-1}) / C_P.
+    Returns (est[21], stderr[21], q float64[P], drawn positions int64[n])."""
+    P = scores.shape[0]
+    C = learned_cdf(scores, lam)
+    CP = C[-1]
+    U = uniform01(seed, 2, n) * CP
+    u = np.searchsorted(C, U, side="right")
+    q = np.diff(np.concatenate([[0.0], C])) / CP
+    wgt = (float(num_wedges) / float(P)) / q[u]
+    cl = close(pool[u])
+    y = cl.astype(np.float64) * wgt[:, None]
+    est = y.sum(axis=0) / n
+    var = (y ** 2).sum(axis=0) - n * est * est
+    se = np.sqrt(np.maximum(var, 0.0) / (n * max(n - 1, 1)))
+    return est, se, q, u
+
+
 def relative_error(est: np.ndarray, exact: np.ndarray):
     """Mean of |H - est| / H over the patterns with H > 0 (the error metric of
     Section 6.3, restricted to patterns that occur), and the per-pattern

@@ -62,6 +62,14 @@ htri_status htri_estimate(htri_graph *h, const htri_sample_params *p, double est
         h->g.err = "defensive_mix must lie in [0, 1] and budget_fraction >= 0";
         return HTRI_E_INVALID;
     }
+    // The network's score is clamped at zero, so without the uniform floor a
+    // hyperwedge scored at or below zero could never be drawn and the
+    // importance weights would no longer cover every closure: unbiasedness
+    // needs a positive draw probability on every hyperwedge.
+    if (p->proposal == 1 && !(p->defensive_mix > 0)) {
+        h->g.err = "the learned proposal needs defensive_mix > 0 (a positive draw probability everywhere)";
+        return HTRI_E_INVALID;
+    }
     return run_g(h, [&] {
         Graph &g = h->g;
         hipStream_t s = g.stream;
@@ -152,6 +160,38 @@ htri_status htri_close_wedges(htri_graph *h, const int64_t *wedge_idx, int64_t n
         HTRI_HIP(hipMemcpyAsync(idx.p, wedge_idx, sizeof(int64_t) * n, hipMemcpyHostToDevice, g.stream));
         close_wedge_list_counts(g, idx.p, n, o.p);
         HTRI_HIP(hipMemcpyAsync(out, o.p, sizeof(int64_t) * n * 21, hipMemcpyDeviceToHost, g.stream));
+        HTRI_HIP(hipStreamSynchronize(g.stream));
+    });
+}
+
+htri_status htri_proposal_scores(htri_graph *h, const htri_model *model, const int64_t *wedge_idx, int64_t n,
+                                 double *out) {
+    if (!h || !model || n < 0 || (n > 0 && !out)) return HTRI_E_INVALID;
+    if (!h->g.have_wedges) {
+        h->g.err = "htri_build_wedges has not run";
+        return HTRI_E_STATE;
+    }
+    if (wedge_idx) {
+        for (int64_t t = 0; t < n; t++)
+            if (wedge_idx[t] < 0 || wedge_idx[t] >= h->g.nw) {
+                h->g.err = "wedge index out of range";
+                return HTRI_E_INVALID;
+            }
+    } else if (n != h->g.nw) {
+        h->g.err = "without a wedge list n must equal the number of hyperwedges";
+        return HTRI_E_INVALID;
+    }
+    return run_g(h, [&] {
+        Graph &g = h->g;
+        if (n == 0) return;
+        DBuf<int64_t> idx;
+        if (wedge_idx) {
+            idx.alloc(g.al, n);
+            HTRI_HIP(hipMemcpyAsync(idx.p, wedge_idx, sizeof(int64_t) * n, hipMemcpyHostToDevice, g.stream));
+        }
+        DBuf<double> sc(g.al, n);
+        score_wedges(g, model, idx.p, n, sc.p);
+        HTRI_HIP(hipMemcpyAsync(out, sc.p, sizeof(double) * n, hipMemcpyDeviceToHost, g.stream));
         HTRI_HIP(hipStreamSynchronize(g.stream));
     });
 }

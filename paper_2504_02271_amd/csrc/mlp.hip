@@ -5,6 +5,9 @@
 // count, mixed with a uniform floor.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
 #include <vector>
 
 #include "internal.hpp"
@@ -240,33 +243,49 @@ __global__ __launch_bounds__(256) void k_fwd_bwd_rows(const float *params, const
     if (threadIdx.x == 0) loss_parts[blockIdx.x] = lsum[0];
 }
 
-// One thread per parameter: sum of the per-row contributions in row order.
-__global__ void k_param_grads(const float *x, const int64_t *rows, int64_t n, const float *H1, const float *H2,
-                              const float *D1, const float *D2, const float *dout, float *grad) {
+// Parameter gradients in two fixed-order passes.  Pass 1: the rows are cut
+// into chunks of `rows_per_chunk`; thread p of chunk c sums row c's
+// contributions to parameter p in row order into part[c][p].  Pass 2: each
+// parameter's chunk partials are summed in chunk order.  Every sum has one
+// order, so the gradient is the same on every run.
+__global__ void k_param_grad_parts(const float *x, const int64_t *rows, int64_t n, int64_t rows_per_chunk,
+                                   const float *H1, const float *H2, const float *D1, const float *D2,
+                                   const float *dout, float *part) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= kNumParams) return;
+    const int64_t c = blockIdx.y;
+    const int64_t b0 = c * rows_per_chunk;
+    const int64_t b1 = b0 + rows_per_chunk < n ? b0 + rows_per_chunk : n;
     float s = 0.f;
     if (p < kOffB1) {
-        const int o = p / kIn, c = p % kIn;
-        for (int64_t b = 0; b < n; b++) {
+        const int o = p / kIn, ci = p % kIn;
+        for (int64_t b = b0; b < b1; b++) {
             const int64_t r = rows ? rows[b] : b;
-            s = fmaf(D1[b * kH + o], x[r * kIn + c], s);
+            s = fmaf(D1[b * kH + o], x[r * kIn + ci], s);
         }
     } else if (p < kOffW2) {
         const int o = p - kOffB1;
-        for (int64_t b = 0; b < n; b++) s += D1[b * kH + o];
+        for (int64_t b = b0; b < b1; b++) s += D1[b * kH + o];
     } else if (p < kOffB2) {
         const int q = p - kOffW2, o = q / kH, i = q % kH;
-        for (int64_t b = 0; b < n; b++) s = fmaf(D2[b * kH + o], H1[b * kH + i], s);
+        for (int64_t b = b0; b < b1; b++) s = fmaf(D2[b * kH + o], H1[b * kH + i], s);
     } else if (p < kOffW3) {
         const int o = p - kOffB2;
-        for (int64_t b = 0; b < n; b++) s += D2[b * kH + o];
+        for (int64_t b = b0; b < b1; b++) s += D2[b * kH + o];
     } else if (p < kOffB3) {
         const int o = p - kOffW3;
-        for (int64_t b = 0; b < n; b++) s = fmaf(dout[b], H2[b * kH + o], s);
+        for (int64_t b = b0; b < b1; b++) s = fmaf(dout[b], H2[b * kH + o], s);
     } else {
-        for (int64_t b = 0; b < n; b++) s += dout[b];
+        for (int64_t b = b0; b < b1; b++) s += dout[b];
     }
+    part[c * kNumParams + p] = s;
+}
+
+__global__ void k_param_grad_sum(const float *part, int nchunks, float *grad) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kNumParams) return;
+    float s = 0.f;
+    for (int c = 0; c < nchunks; c++) s += part[(int64_t)c * kNumParams + p];
     grad[p] = s;
 }
 
@@ -321,16 +340,26 @@ void score_wedges(Graph &g, const htri_model *model, const int64_t *dev_wedges, 
 namespace {
 
 // loss and gradient over rows (all n rows, or a minibatch given by `rows`)
+constexpr int64_t kGradRowsPerChunk = 64;
+constexpr int64_t kGradMaxChunks = 512;
+
 struct GradBufs {
-    DBuf<float> H1, H2, D1, D2, dout;
+    DBuf<float> H1, H2, D1, D2, dout, part;
     DBuf<double> lp;
     int grid = 1;
     GradBufs(Allocator &A, int64_t n) : H1(A, n * kH), H2(A, n * kH), D1(A, n * kH), D2(A, n * kH), dout(A, n) {
         grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
         if (grid < 1) grid = 1;
         lp.alloc(A, grid);
+        part.alloc(A, (size_t)kGradMaxChunks * kNumParams);
     }
 };
+
+// rows per chunk and chunk count of the gradient's first pass for n rows
+inline void grad_chunks(int64_t n, int64_t &rows_per_chunk, int &nchunks) {
+    rows_per_chunk = std::max<int64_t>(kGradRowsPerChunk, (n + kGradMaxChunks - 1) / kGradMaxChunks);
+    nchunks = (int)std::max<int64_t>(1, (n + rows_per_chunk - 1) / rows_per_chunk);
+}
 
 double loss_grad(htri_model *mdl, GradBufs &B, const float *x, const float *y, const int64_t *rows, int64_t n,
                  float *grad_dev) {
@@ -339,8 +368,13 @@ double loss_grad(htri_model *mdl, GradBufs &B, const float *x, const float *y, c
     hipLaunchKernelGGL(k_fwd_bwd_rows, dim3(grid), dim3(256), 0, s, mdl->params.p, x, y, rows, n, 1.0f / (float)n,
                        B.H1.p, B.H2.p, B.D1.p, B.D2.p, B.dout.p, B.lp.p);
     HTRI_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_param_grads, dim3((kNumParams + 255) / 256), dim3(256), 0, s, x, rows, n, B.H1.p, B.H2.p,
-                       B.D1.p, B.D2.p, B.dout.p, grad_dev);
+    int64_t rpc;
+    int nch;
+    grad_chunks(n, rpc, nch);
+    hipLaunchKernelGGL(k_param_grad_parts, dim3((kNumParams + 255) / 256, nch), dim3(256), 0, s, x, rows, n, rpc,
+                       B.H1.p, B.H2.p, B.D1.p, B.D2.p, B.dout.p, B.part.p);
+    HTRI_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_param_grad_sum, dim3((kNumParams + 255) / 256), dim3(256), 0, s, B.part.p, nch, grad_dev);
     HTRI_LAUNCH_CHECK();
     std::vector<double> h(grid);
     HTRI_HIP(hipMemcpyAsync(h.data(), B.lp.p, sizeof(double) * grid, hipMemcpyDeviceToHost, s));
@@ -430,6 +464,86 @@ htri_status htri_model_set_params(htri_model *m, const float *host_params) {
         m->adam_t = 0;
         HTRI_HIP(hipStreamSynchronize(m->stream));
     });
+}
+
+// Metadata written beside the raw parameters; a load accepts only files whose
+// metadata names this layout.
+static const char kModelMeta[] =
+    "{\"format\": \"htri-proposal-mlp\", \"version\": 1, \"layers\": [16, 64, 64, 1], "
+    "\"activation\": \"relu\", \"dtype\": \"float32\", \"byte_order\": \"little\", "
+    "\"num_params\": 5313, \"layout\": [\"W1[64][16]\", \"b1[64]\", \"W2[64][64]\", \"b2[64]\", "
+    "\"w3[64]\", \"b3\"]}\n";
+
+const char *htri_model_last_error(const htri_model *m) { return m ? m->err.c_str() : ""; }
+
+htri_status htri_model_save(const htri_model *mc, const char *path) {
+    htri_model *m = const_cast<htri_model *>(mc);
+    if (!m || !path || !*path) return HTRI_E_INVALID;
+    std::vector<float> p(kNumParams);
+    htri_status st = htri_model_get_params(m, p.data());
+    if (st != HTRI_OK) return st;
+    const std::string meta = std::string(path) + ".json";
+    FILE *f = std::fopen(path, "wb");
+    if (!f) {
+        m->err = std::string("cannot open ") + path + " for writing";
+        return HTRI_E_INVALID;
+    }
+    const bool ok = std::fwrite(p.data(), sizeof(float), kNumParams, f) == (size_t)kNumParams;
+    if (std::fclose(f) != 0 || !ok) {
+        m->err = std::string("short write to ") + path;
+        return HTRI_E_INVALID;
+    }
+    FILE *j = std::fopen(meta.c_str(), "wb");
+    if (!j) {
+        m->err = "cannot open " + meta + " for writing";
+        return HTRI_E_INVALID;
+    }
+    const size_t len = sizeof(kModelMeta) - 1;
+    const bool ok2 = std::fwrite(kModelMeta, 1, len, j) == len;
+    if (std::fclose(j) != 0 || !ok2) {
+        m->err = "short write to " + meta;
+        return HTRI_E_INVALID;
+    }
+    return HTRI_OK;
+}
+
+htri_status htri_model_load(htri_model *m, const char *path) {
+    if (!m || !path || !*path) return HTRI_E_INVALID;
+    const std::string meta = std::string(path) + ".json";
+    FILE *j = std::fopen(meta.c_str(), "rb");
+    if (!j) {
+        m->err = "cannot open " + meta;
+        return HTRI_E_INVALID;
+    }
+    std::string text;
+    char buf[512];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof(buf), j)) > 0 && text.size() < 65536) text.append(buf, got);
+    std::fclose(j);
+    if (text.find("\"htri-proposal-mlp\"") == std::string::npos ||
+        text.find("\"num_params\": 5313") == std::string::npos ||
+        text.find("\"float32\"") == std::string::npos) {
+        m->err = meta + " does not describe a 16-64-64-1 float32 proposal network";
+        return HTRI_E_INVALID;
+    }
+    FILE *f = std::fopen(path, "rb");
+    if (!f) {
+        m->err = std::string("cannot open ") + path;
+        return HTRI_E_INVALID;
+    }
+    std::vector<float> p(kNumParams + 1);
+    const size_t n = std::fread(p.data(), sizeof(float), kNumParams + 1, f);
+    std::fclose(f);
+    if (n != (size_t)kNumParams) {
+        m->err = std::string(path) + " does not hold exactly 5313 float32 parameters";
+        return HTRI_E_INVALID;
+    }
+    for (int i = 0; i < kNumParams; i++)
+        if (!std::isfinite(p[i])) {
+            m->err = std::string(path) + " holds a non-finite parameter";
+            return HTRI_E_INVALID;
+        }
+    return htri_model_set_params(m, p.data());
 }
 
 htri_status htri_model_forward(const htri_model *mc, const float *dev_x, int64_t n, float *dev_out) {

@@ -248,21 +248,40 @@ __global__ __launch_bounds__(kBlock) void k_sample_close(SampleArgs A) {
     }
 }
 
-// fixed-order reduction of the per-wave accumulators
-__global__ void k_sample_reduce(const long long *acc_c, const double *acc_y, const double *acc_y2, int64_t nwaves,
-                                long long *c, double *y, double *y2) {
-    const int p = threadIdx.x;
-    if (p >= 21) return;
+// Fixed-order reduction of the per-wave accumulators: block p reduces
+// pattern p; thread t sums waves t, t + 256, ... in order, then the block
+// adds the 256 partial sums pairwise in a fixed tree.
+constexpr int kReduceThreads = 256;
+__global__ __launch_bounds__(kReduceThreads) void k_sample_reduce(const long long *acc_c, const double *acc_y,
+                                                                  const double *acc_y2, int64_t nwaves, long long *c,
+                                                                  double *y, double *y2) {
+    __shared__ long long sc[kReduceThreads];
+    __shared__ double sy[kReduceThreads], sy2[kReduceThreads];
+    const int p = blockIdx.x, t = threadIdx.x;
     long long s = 0;
     double a = 0, b = 0;
-    for (int64_t w = 0; w < nwaves; w++) {
+    for (int64_t w = t; w < nwaves; w += kReduceThreads) {
         s += acc_c[w * 21 + p];
         a += acc_y[w * 21 + p];
         b += acc_y2[w * 21 + p];
     }
-    c[p] = s;
-    y[p] = a;
-    y2[p] = b;
+    sc[t] = s;
+    sy[t] = a;
+    sy2[t] = b;
+    __syncthreads();
+    for (int o = kReduceThreads / 2; o > 0; o >>= 1) {
+        if (t < o) {
+            sc[t] += sc[t + o];
+            sy[t] += sy[t + o];
+            sy2[t] += sy2[t + o];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        c[p] = sc[0];
+        y[p] = sy[0];
+        y2[p] = sy2[0];
+    }
 }
 
 __global__ void k_pool_draw(uint64_t seed, int64_t pool_n, int64_t nw, int64_t *pool) {
@@ -349,7 +368,8 @@ void sample_sums(Graph &g, int mode, int64_t n, uint64_t seed, const int64_t *po
     HTRI_LAUNCH_CHECK();
     DBuf<long long> dc(A, 21);
     DBuf<double> dy(A, 21), dy2(A, 21);
-    hipLaunchKernelGGL(k_sample_reduce, dim3(1), dim3(64), 0, s, ac.p, ay.p, ay2.p, nwaves, dc.p, dy.p, dy2.p);
+    hipLaunchKernelGGL(k_sample_reduce, dim3(21), dim3(kReduceThreads), 0, s, ac.p, ay.p, ay2.p, nwaves, dc.p, dy.p,
+                       dy2.p);
     HTRI_LAUNCH_CHECK();
     HTRI_HIP(hipMemcpyAsync(c, dc.p, sizeof(long long) * 21, hipMemcpyDeviceToHost, s));
     HTRI_HIP(hipMemcpyAsync(y, dy.p, sizeof(double) * 21, hipMemcpyDeviceToHost, s));

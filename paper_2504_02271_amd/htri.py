@@ -115,6 +115,10 @@ def load_library() -> ctypes.CDLL:
         "htri_subgraph": ([_P, ctypes.c_double, _u64, _i32, ctypes.POINTER(_P), _P, _P, _P], ctypes.c_int),
         "htri_close_wedges": ([_P, _P, _i64, _P], ctypes.c_int),
         "htri_wedge_features": ([_P, _P], ctypes.c_int),
+        "htri_proposal_scores": ([_P, _P, _P, _i64, _P], ctypes.c_int),
+        "htri_model_save": ([_P, ctypes.c_char_p], ctypes.c_int),
+        "htri_model_load": ([_P, ctypes.c_char_p], ctypes.c_int),
+        "htri_model_last_error": ([_P], ctypes.c_char_p),
         "htri_model_create": ([_u64, _P, ctypes.POINTER(_P)], ctypes.c_int),
         "htri_model_free": ([_P], None),
         "htri_model_get_params": ([_P, _P], ctypes.c_int),
@@ -356,6 +360,21 @@ class Graph:
                "htri_close_wedges", self._h)
         return out
 
+    def proposal_scores(self, model: "Model", idx=None) -> np.ndarray:
+        """float64 score of the learned proposal for the listed hyperwedges
+        (get_wedges order; None = every hyperwedge)."""
+        if idx is None:
+            n = self.num_wedges
+            idx_p = None
+        else:
+            idx = np.ascontiguousarray(idx, dtype=np.int64)
+            n = idx.shape[0]
+            idx_p = _ptr(idx)
+        out = np.zeros(max(n, 1), np.float64)
+        _check(self._lib.htri_proposal_scores(self._h, model._h, idx_p, n, _ptr(out)),
+               "htri_proposal_scores", self._h)
+        return out[:n]
+
     def wedge_features(self):
         """float32 [|wedges|, 16] torch tensor on the GPU."""
         import torch
@@ -442,6 +461,18 @@ class Model:
         params = np.ascontiguousarray(params, dtype=np.float32)
         assert params.shape == (HTRI_MODEL_NUM_PARAMS,)
         _check(self._lib.htri_model_set_params(self._h, _ptr(params)), "htri_model_set_params")
+
+    def _merr(self, rc, where):
+        if rc != HTRI_OK:
+            msg = self._lib.htri_model_last_error(self._h)
+            raise HtriError(rc, where, msg.decode() if msg else "")
+
+    def save(self, path: str) -> None:
+        """Raw float32 parameters at path, JSON metadata at path + '.json'."""
+        self._merr(self._lib.htri_model_save(self._h, os.fsencode(path)), "htri_model_save")
+
+    def load(self, path: str) -> None:
+        self._merr(self._lib.htri_model_load(self._h, os.fsencode(path)), "htri_model_load")
 
     def forward(self, x):
         import torch

@@ -29,3 +29,25 @@ def load_golden(name):
             elif line == "complete":
                 complete = True
     return edges, tris, complete
+
+
+_EXPECTED = None
+
+
+def expected_counts(sha256):
+    """The oracle's stored exact counts for an input (tests/golden/
+    expected_counts.json, written by tests/golden/make_expected_counts.py
+    from the CPU oracle alone), keyed by the input's SHA-256; None if absent."""
+    global _EXPECTED
+    if _EXPECTED is None:
+        import json
+        with open(os.path.join(ROOT, "tests", "golden", "expected_counts.json")) as fh:
+            _EXPECTED = json.load(fh)
+    return _EXPECTED.get(sha256)
+
+
+def int64_digest(a):
+    """SHA-256 of an int64 array's little-endian bytes (as the stored t digests)."""
+    import hashlib
+    import numpy as np
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<i8").tobytes()).hexdigest()

@@ -79,7 +79,7 @@ def count_one(hg: synth.HyperGraph, workload: str, threads: int, chunks: int,
     sha = hg.sha256()
     t0 = time.time()
     og = oc.OracleGraph(hg.offsets, hg.members, hg.num_vertices, dedupe=True)
-    og.build_wedges()
+    og.build_wedges(nthreads=threads)
     summ = og.summary()
     log(f"{workload}: m={og.m} wedges={summ[0]} W={summ[3]} step1 {time.time() - t0:.1f}s")
     m = og.m

@@ -267,3 +267,60 @@ def test_clustering_coefficient_closed_forms():
     bad[3] = 1.5
     with pytest.raises(htri.HtriError):
         htri.clustering_coefficient(H, W, bad)
+
+
+# ---------------------------------------------------------------- learned proposal replay
+
+def _tiny_closures():
+    """Forward closures of every hyperwedge of a small hypergraph in id order,
+    by the brute-force triple scan (patterns by canonical region masks)."""
+    from oracle import brute
+    g = synth.random_small(2, 40, 12, 1, 5)
+    E = brute.normalise([g.edge(x).tolist() for x in range(g.num_edges)])
+    wedges = [(i, j) for i in range(len(E)) for j in range(i + 1, len(E)) if E[i] & E[j]]
+    cl = np.zeros((len(wedges), 21), np.int64)
+    for w, (i, j) in enumerate(wedges):
+        for k in range(j + 1, len(E)):
+            if E[i] & E[k] and E[j] & E[k]:
+                p = brute.pattern_of(E[i], E[j], E[k])
+                cl[w, p] += 1
+                cl[w, 0] += 1
+    H = cl.sum(axis=0)
+    return cl, H
+
+
+def test_learned_estimator_arithmetic():
+    """The learned-proposal replay: probabilities sum to 1 and are positive
+    with a uniform floor; with lam = 1 it is the uniform estimate over the
+    pool; the draws follow q; and its mean over many seeds is unbiased for
+    the brute-force counts (Lemma 4.1 with importance weights)."""
+    cl, H = _tiny_closures()
+    nw = cl.shape[0]
+    rng = np.random.default_rng(0)
+    scores = np.where(rng.random(nw) < 0.3, 0.0, rng.exponential(3.0, nw))
+    pool = np.arange(nw, dtype=np.int64)
+    close = lambda idx: cl[idx]
+    est, se, q, u = sampling.learned_estimate(scores, pool, nw, 0.1, 7, 5000, close)
+    assert abs(q.sum() - 1.0) < 1e-12 and (q > 0).all()
+    assert (q[scores == 0] > 0).all()
+    # lam = 1: the uniform estimate of the drawn pool members
+    est1, _, q1, u1 = sampling.learned_estimate(scores, pool, nw, 1.0, 3, 4000, close)
+    assert np.allclose(q1, 1.0 / nw, rtol=1e-12)
+    assert np.allclose(est1, cl[u1].sum(axis=0) * nw / 4000.0, rtol=1e-12)
+    # draws follow q: chi-square over the pool
+    counts = np.bincount(u, minlength=nw)
+    exp = 5000 * q
+    chi2 = ((counts - exp) ** 2 / exp).sum()
+    assert chi2 < nw + 6 * np.sqrt(2 * nw), chi2
+    # a uniform pool of half the wedges: unbiased for H over pool draws
+    R = 400
+    ests = []
+    for s in range(R):
+        pl = sampling.uniform_indices(1000 + s, 1, nw // 2, nw)
+        ests.append(sampling.learned_estimate(scores[pl], pl, nw, 0.2, 2000 + s, 300, close)[0])
+    ests = np.array(ests)
+    m = ests.mean(axis=0)
+    sem = ests.std(axis=0, ddof=1) / np.sqrt(R)
+    for p in range(21):
+        if H[p] > 0:
+            assert abs(m[p] - H[p]) < 4.5 * sem[p] + 1e-9, (p, m[p], H[p], sem[p])

@@ -1,10 +1,13 @@
 """Parity at the full benchmark size (tags-shaped, |V|=1e6, |E|=5e6, the
-launch configuration bench.py times): per-wedge closures and per-hyperedge
-counts on samples the oracle computes one by one, and invariants of the
-whole count."""
+launch configuration bench.py times): every per-pattern count and every
+per-hyperedge count against the oracle's full count (stored once by
+tests/golden/make_expected_counts.py, keyed by the input's SHA-256),
+per-wedge closures on samples the oracle computes one by one, and
+invariants of the whole count."""
 import numpy as np
 import pytest
 
+from conftest import expected_counts, int64_digest
 from oracle import core
 from paper_2504_02271_amd import synth
 
@@ -30,6 +33,37 @@ def full():
     rank = core.prec_rank(off, mem, g.num_vertices)
     return dict(g=g, G=G, s=s, counts=counts, pe=pe, pw=pw, src=src, dst=dst, om=om, o=o, off=off, mem=mem,
                 rank=rank)
+
+
+def test_counts_equal_the_oracle_full_count(full):
+    """All 20 per-pattern counts bit-exact, and the per-hyperedge counts of
+    all 5M hyperedges element by element (through their SHA-256), against
+    the oracle's plain two-step count of the same input."""
+    rec = expected_counts(full["g"].sha256())
+    assert rec is not None, "no stored oracle count for this input"
+    assert list(full["s"]) == rec["summary"]
+    assert full["counts"].tolist() == rec["H"]
+    assert int(full["pe"].sum()) == rec["t_sum"]
+    for x, tx in rec["t_sample"]:
+        assert int(full["pe"][x]) == tx, x
+    assert int64_digest(full["pe"]) == rec["t_sha256"]
+    print(f"\n[fullsize] H and t equal the oracle's full count ({rec['H'][0]} triangles)", flush=True)
+
+
+def test_estimator_graph_counts_equal_the_oracle():
+    """The samplers' evaluation graph (tags shape, seed 5): its exact count,
+    which judges every estimate, equals the oracle's full count."""
+    from paper_2504_02271_amd import htri
+    g = synth.generate(synth.config("tags_eval"))
+    rec = expected_counts(g.sha256())
+    assert rec is not None, "no stored oracle count for this input"
+    G = htri.graph_load(g.offsets, g.members, g.num_vertices)
+    s = G.build_wedges()
+    counts, pe, _ = G.count_patterns(per_edge=True)
+    assert list(s) == rec["summary"]
+    assert counts.tolist() == rec["H"]
+    assert int64_digest(pe) == rec["t_sha256"]
+    G.close()
 
 
 def test_window_and_probing_agree(full):

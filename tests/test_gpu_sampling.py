@@ -224,3 +224,119 @@ def test_exact_inclusion_stratum_unbiased(htri):
             # sample standard error is then no guide, so it is not tested
             if H[p] > 0 and se[p] > 0 and (ests[:, p] != 0).mean() >= 0.5:
                 assert abs(mean[p] - H[p]) < 4.5 * se[p], (proposal, p, mean[p], H[p], se[p])
+
+
+# ---------------------------------------------------------------- learned proposal, exact replay
+
+def _inclusion_mask(o, lo, hi):
+    """Inclusion type (omega = smaller size) of each listed hyperwedge, from
+    the oracle's own hyperwedge list."""
+    wi, wj, wo = o.wedges()
+    off, _, _ = o.csr()
+    size = np.diff(off)
+    key = lambda a, b: np.minimum(a, b).astype(np.int64) * (1 << 32) + np.maximum(a, b)
+    k_or = key(wi, wj)
+    order = np.argsort(k_or, kind="stable")
+    pos = np.searchsorted(k_or[order], key(lo, hi))
+    omega = wo[order][pos]
+    return omega == np.minimum(size[lo], size[hi])
+
+
+@pytest.mark.parametrize("pool_factor,lam,exact_incl", [(0.0, 0.1, False), (8.0, 0.1, False),
+                                                        (8.0, 0.5, True), (0.0, 0.3, True)])
+def test_learned_estimate_matches_oracle_replay(htri, pool_factor, lam, exact_incl):
+    """The learned estimate replayed on the CPU from the same Philox pool and
+    draws and the library's proposal scores: float64 CDF, inverse-CDF draws,
+    realised probabilities and the Hansen-Hurwitz sum of the oracle's
+    closures agree with htri_estimate.
+
+    Tolerance: q_u = (C_u - C_{u-1}) / C_P is a difference of two prefix
+    sums of the order of C_P, each carrying a rounding error of about
+    2^-53 C_P that depends on the summation order (the library scans in
+    parallel, the replay sequentially), so q_u -- about C_P / P -- agrees to
+    a few P * 2^-53 relative; the estimate, a weighted mean of closures over
+    q, inherits that bound.  8 P 2^-53 is used (1.5e-9 at P = 1.7e6)."""
+    g = synth.generate(synth.config("coauth", 0.1))
+    G, o, rank = _setup(htri, g)
+    m = htri.Model(seed=2)
+    wi, wj, _ = o.wedges()
+    lo, hi = sampling.prec_wedge_order(rank, wi, wj)
+    nw = lo.shape[0]
+    incl = _inclusion_mask(o, lo, hi)
+    exact = o.wedge_closure_ranked(rank, lo[incl], hi[incl]).sum(axis=0).astype(np.float64)
+
+    def close(idx):
+        cl = o.wedge_closure_ranked(rank, lo[idx], hi[idx])
+        if exact_incl:
+            cl[incl[idx]] = 0
+        return cl
+
+    for seed, n in ((0, 1500), (11, 12000)):
+        est, se, _ = G.estimate(num_samples=n, seed=seed, proposal=1, model=m, defensive_mix=lam,
+                                pool_factor=pool_factor, exact_inclusion=exact_incl)
+        if pool_factor > 0:
+            P = int(np.floor(pool_factor * n + 0.5))
+            pool = sampling.uniform_indices(seed, 1, P, nw)
+        else:
+            pool = np.arange(nw, dtype=np.int64)
+        scores = G.proposal_scores(m, pool)
+        assert (scores >= 0).all()
+        want, wse, q, u = sampling.learned_estimate(scores, pool, nw, lam, seed, n, close)
+        assert abs(q.sum() - 1.0) < 1e-12 and (q[u] > 0).all() and (q > 0).all()
+        if exact_incl:
+            want = want + exact
+        rtol = 8.0 * pool.shape[0] * 2.0 ** -53
+        rel = np.abs(est - want) / np.maximum(np.abs(want), 1e-300)
+        print(f"\n[learned replay] P={pool.shape[0]} n={n} max rel diff {rel[want != 0].max():.3e} "
+              f"(tolerance {rtol:.1e})", flush=True)
+        assert np.allclose(est, want, rtol=rtol, atol=1e-9), (seed, est, want)
+        assert np.allclose(se, wse, rtol=1e-9, atol=1e-6)
+    # the scores themselves against the float64 network on float64 features
+    off, mem, _ = o.csr()
+    wo = o.wedges()[2]
+    pick = np.random.default_rng(5).choice(nw, size=1500, replace=False)
+    X = features_ref.features(off, mem, g.num_vertices, rank, wi, wj, wo, lo[pick], hi[pick])
+    f = mlp_ref.forward(m.get_params().astype(np.float64), X)
+    ref = np.expm1(np.clip(f, 0.0, 30.0))
+    assert np.allclose(G.proposal_scores(m, pick), ref, rtol=1e-3, atol=1e-4)
+
+
+def test_learned_estimate_refuses_zero_floor(htri):
+    """Without the uniform floor (lambda = 0) a hyperwedge the network scores
+    at or below zero could never be drawn: the library refuses it."""
+    g = synth.generate(synth.config("tiny"))
+    G, _, _ = _setup(htri, g)
+    m = htri.Model(seed=1)
+    with pytest.raises(htri.HtriError) as e:
+        G.estimate(num_samples=100, seed=0, proposal=1, model=m, defensive_mix=0.0)
+    assert e.value.code == -1 and "defensive_mix" in str(e.value)
+    est, _, _ = G.estimate(num_samples=100, seed=0, proposal=1, model=m, defensive_mix=1e-6)
+    assert np.isfinite(est).all()
+
+
+def test_model_save_load_round_trip(htri, tmp_path):
+    """Raw float32 parameters plus JSON metadata: a saved model loads back
+    bit for bit; a truncated file or foreign metadata is refused."""
+    import json
+    m = htri.Model(seed=11)
+    path = str(tmp_path / "proposal.f32")
+    m.save(path)
+    meta = json.load(open(path + ".json"))
+    assert meta["num_params"] == htri.HTRI_MODEL_NUM_PARAMS and meta["layers"] == [16, 64, 64, 1]
+    raw = np.fromfile(path, dtype="<f4")
+    assert np.array_equal(raw, m.get_params())
+    m2 = htri.Model(seed=99)
+    m2.load(path)
+    assert np.array_equal(m2.get_params(), m.get_params())
+    with open(path, "r+b") as fh:
+        fh.truncate(4 * 100)
+    with pytest.raises(htri.HtriError) as e:
+        m2.load(path)
+    assert e.value.code == -1
+    bad = str(tmp_path / "other.f32")
+    raw.tofile(bad)
+    with open(bad + ".json", "w") as fh:
+        fh.write('{"format": "something-else"}')
+    with pytest.raises(htri.HtriError):
+        m2.load(bad)
+    assert np.array_equal(m2.get_params(), m.get_params())

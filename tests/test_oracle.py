@@ -182,6 +182,7 @@ def test_oracle_matches_brute_force(seed):
     edges = [g.edge(x).tolist() for x in range(g.num_edges)]
     H, t = brute.count(edges)
     o = core.OracleGraph(g.offsets, g.members, g.num_vertices)
+    o.build_wedges(nthreads=1 + seed % 4)        # step 1 split over 1-4 threads
     r = o.count(nthreads=3, per_wedge=True)
     assert (r.H == H).all()
     assert (r.t == t).all()
