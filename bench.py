@@ -187,37 +187,110 @@ def batch_study(log_fn, repeats: int = 5):
     }
 
 
-def cpu_baseline(g, seconds: float, seed: int = 11):
-    """The CPU oracle (plain two-step count from the vertex lists) on a random
-    sample of owners of the same hypergraph, timed on the host cores."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _host_threads() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def _stored_oracle_count(sha256: str):
+    """The oracle's full count of an input, written once on the CPU by
+    tests/golden/make_expected_counts.py (None when absent)."""
+    path = os.path.join(ROOT, "tests", "golden", "expected_counts.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f).get(sha256)
+
+
+def _owner_ranges(m: int, pieces: int, per_piece: int):
+    """`pieces` owner ranges of `per_piece` owners at evenly spaced starts."""
+    return [(k * m // pieces, min(m, k * m // pieces + per_piece)) for k in range(pieces)]
+
+
+def cpu_baseline(g, workload: str, log_fn):
+    """The CPU oracle as it stands -- the plain two-step count (normalise;
+    step 1 with threads over owners, as Par-adv; closure by merging sorted
+    neighbour lists; g by merging member lists; rule-based classification)
+    -- timed with a steady clock on the host cores, on the same hypergraph.
+
+    Bounded sample: normalisation and step 1 run over the whole hypergraph;
+    the closure runs over 16 owner ranges at evenly spaced starts, 1/256 of
+    the owners with every thread and 1/4096 with one.  The oracle's closure
+    costs about the same per hyper-triangle anywhere, so the whole closure's
+    time is the sample's scaled by the sample's share of the
+    hyper-triangles, whose total comes from the oracle's own stored full
+    count of this input (never from the GPU)."""
     from oracle import core
-    threads = max(1, min(16, os.cpu_count() or 1))
-    t0 = time.time()
+    threads = _host_threads()
+    rec = _stored_oracle_count(g.sha256())
+    T_total = rec["H"][0] if rec else None
+    t0 = time.perf_counter()
     o = core.OracleGraph(g.offsets, g.members, g.num_vertices)
-    norm_s = time.time() - t0
-    rng = np.random.default_rng(seed)
-    n_try = 64
-    owners = rng.permutation(o.m).astype(np.int32)
-    used = 0
-    tot_w = 0
-    tot_t = 0.0
-    # grow the sample until the time budget is spent
-    while used < o.m and tot_t < seconds:
-        n = min(n_try, o.m - used)
-        batch = owners[used:used + n]
-        t1 = time.time()
-        _, nw = o.count_owner_sample(batch, nthreads=threads)
-        dt = time.time() - t1
-        tot_w += nw
-        tot_t += dt
-        used += n
-        n_try = min(n_try * 2, 1 << 20)
-    rate = tot_w / tot_t if tot_t > 0 else 0.0
-    return {"value": rate, "unit": "hyperwedges/s", "cores": threads, "kind": "oracle",
-            "sample": f"{used} of {o.m} owners drawn uniformly (seed {seed}), every hyperwedge of "
-                      f"each closed by the plain two-step oracle from the vertex lists; "
-                      f"{tot_w} hyperwedges in {tot_t:.1f} s ({threads} threads; "
-                      f"normalisation {norm_s:.1f} s not counted)"}
+    norm_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    o.build_wedges(nthreads=threads)
+    step1_s = time.perf_counter() - t0
+    summ = o.summary()
+    nw = int(summ[0])
+    log_fn(f"[bench] oracle: normalise {norm_s:.1f} s, step 1 {step1_s:.1f} s on {threads} threads")
+
+    def closure_sample(ranges, nthreads):
+        T = 0
+        t1 = time.perf_counter()
+        for a, b in ranges:
+            T += int(o.count_range(a, b, nthreads=nthreads, per_edge=False).H[0])
+        return T, time.perf_counter() - t1
+
+    res = {}
+    for label, nthreads, per in (("all_threads", threads, o.m // 4096), ("one_thread", 1, o.m // 65536)):
+        ranges = _owner_ranges(o.m, 16, max(1, per))
+        T_s, close_s = closure_sample(ranges, nthreads)
+        owners = sum(b - a for a, b in ranges)
+        share = T_s / T_total if T_total else None
+        close_full_s = close_s / share if share else None
+        res[label] = {"threads": nthreads, "sample_owners": owners, "sample_triangles": T_s,
+                      "sample_closure_s": round(close_s, 3),
+                      "triangle_share": share,
+                      "closure_whole_graph_s_scaled": close_full_s,
+                      "ns_per_triangle_thread": close_s * nthreads / T_s * 1e9 if T_s else None}
+        log_fn(f"[bench] oracle closure sample ({label}): {owners} owners, {T_s} triangles, {close_s:.1f} s")
+    a = res["all_threads"]
+    total_s = norm_s + step1_s + a["closure_whole_graph_s_scaled"] if a["closure_whole_graph_s_scaled"] else None
+    o1 = res["one_thread"]
+    return {
+        "value": nw / total_s if total_s else None,
+        "unit": "hyperwedges/s",
+        "cores": threads,
+        "kind": "oracle",
+        "workload": f"the benchmark's own hypergraph ({workload})",
+        "cpu_model": _cpu_model(),
+        "nproc": os.cpu_count(),
+        "sample": (f"plain two-step oracle: normalise {norm_s:.2f} s (1 thread) and step 1 {step1_s:.2f} s "
+                   f"({threads} threads) over all {o.m} hyperedges; closure over 16 evenly spaced owner "
+                   f"ranges ({a['sample_owners']} owners, {a['sample_triangles']} hyper-triangles) in "
+                   f"{a['sample_closure_s']} s on {threads} threads, scaled by the sample's share "
+                   f"{a['triangle_share']} of the oracle's stored total {T_total}; value = {nw} hyperwedges / "
+                   f"(normalise + step 1 + scaled closure)"),
+        "whole_count_s_estimate": total_s,
+        "normalise_s": round(norm_s, 3),
+        "step1_s": round(step1_s, 3),
+        "closure": res,
+        "one_thread_closure_rate_triangles_per_s": o1["sample_triangles"] / o1["sample_closure_s"]
+        if o1["sample_closure_s"] else None,
+    }
 
 
 def main() -> int:
@@ -226,7 +299,6 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="tags", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-study", action="store_true", help="skip the learned-vs-uniform estimator study")
     ap.add_argument("--study-seeds", type=int, default=32)
@@ -315,9 +387,9 @@ def main() -> int:
 
     cpu = None
     if not args.no_cpu:
-        log("[bench] timing the CPU oracle on an owner sample ...")
-        cpu = cpu_baseline(g, args.cpu_seconds)
-        log(f"[bench] CPU oracle: {cpu['value']:.3e} hyperwedges/s")
+        log("[bench] timing the CPU oracle ...")
+        cpu = cpu_baseline(g, args.workload, log)
+        log(f"[bench] CPU oracle: {cpu['value']} hyperwedges/s")
 
     study = None
     if not args.no_study:

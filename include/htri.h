@@ -254,7 +254,7 @@ typedef struct {
     double budget_fraction;   /* samples = budget_fraction * |wedges| ...      */
     int64_t num_samples;      /* ... unless num_samples > 0                    */
     uint64_t seed;            /* Philox-4x32-10 key                            */
-    int32_t proposal;         /* 0 = uniform, 1 = learned                      */
+    int32_t proposal;         /* 0 = uniform, 1 = learned, 2 = split by type   */
     int32_t flags;            /* HTRI_SAMPLE_EXACT_INCLUSION or 0              */
     const htri_model *model;  /* required for proposal 1                       */
     double defensive_mix;     /* lambda: q = (1-lambda) q_model + lambda/|pool| */
@@ -266,7 +266,8 @@ typedef struct {
 } htri_sample_params;
 
 /* Hyperwedge-sampling estimate (Algorithm 6, sigma = 1; unbiased by Lemma
- * 4.1, and for any positive proposal by importance weighting).
+ * 4.1, and for any positive proposal by importance weighting; proposal 2 is
+ * Algorithm 7, Appro-adv).
  *   proposal 0 (uniform): n draws w_t = floor(u_t * |wedges| / 2^64) with u_t
  *     the 64-bit word t of Philox stream 0 under `seed`;
  *     est_p = (|wedges| / n) * sum_t c_p(w_t), c_p(w) = the third hyperedges
@@ -279,6 +280,20 @@ typedef struct {
  *     U_t = (word t of Philox stream 2 >> 11) * 2^-53, with the realised
  *     probability q_u = (C_u - C_{u-1}) / C_P, and
  *     est_p = (|wedges| / P) * (1/n) * sum_t c_p(pool[u_t]) / q_{u_t}.
+ *   proposal 2 (Appro-adv, Algorithm 7, Section 4.2): the budget of n draws
+ *     is split by the hyperwedge types (htri_adv_split): alpha1 draws from
+ *     the |T| intersection hyperwedges (Philox stream 8) estimate patterns
+ *     9-20 (TTT), alpha2 from the |C| inclusion ones (stream 9) pattern 1
+ *     (CCC), alpha3 from T (stream 10) patterns 6-8 (TTC) and alpha4 from C
+ *     (stream 11) patterns 2-5 (TCC).  Draw t of a list takes its element
+ *     floor(u_t * size / 2^64) (T: the positions of htri_get_wedges that
+ *     hold no inclusion hyperwedge, in order; C: those that do).  A draw
+ *     counts the hyper-triangles of its class for which it is the earliest
+ *     hyperwedge of its type (hyperwedges ordered by their rank pairs), and
+ *     est_p = (list size / alpha_i) * sum of the draws' counts.  stderr_[p]
+ *     per pattern; stderr_[0] adds the per-pattern variances (the classes
+ *     are independent; within a class the covariance is left out).
+ *     Not combinable with HTRI_SAMPLE_EXACT_INCLUSION.
  *   With HTRI_SAMPLE_EXACT_INCLUSION, drawn inclusion hyperwedges close
  *   nothing and the exact closures of all inclusion hyperwedges are added.
  *   est       double[21] host array: estimated H, [0] = total.
@@ -288,6 +303,14 @@ typedef struct {
  * lambda <= 0 with proposal 1), HTRI_E_OOM, HTRI_E_DEVICE. */
 htri_status htri_estimate(htri_graph *g, const htri_sample_params *p, double est[21],
                           double stderr_[21], double *time_ms);
+
+/* Appro-adv's split of a budget of alpha draws by hyperwedge type
+ * (Algorithm 7, line 4): out[0] = alpha1 = |T|^2 alpha / |W|^2 (TTT),
+ * out[1] = alpha2 = |C|^2 alpha / |W|^2 (CCC), out[2] = alpha3 and out[3] =
+ * alpha4 = |T| |C| alpha / |W|^2 (TTC, TCC), with |W| = |T| + |C|, each
+ * rounded half up and at least 1 when its lists are non-empty (the paper
+ * leaves the rounding open), 0 otherwise.  Host arithmetic only. */
+htri_status htri_adv_split(int64_t n_inter, int64_t n_incl, int64_t alpha, int64_t out[4]);
 
 /* Sub-hypergraph for sigma-sampling (Algorithm 6, with sigma in (0, 1]: the
  * hyperedges are subsampled before the hyperwedges are, and the estimate is

@@ -130,6 +130,82 @@ def learned_estimate(scores: np.ndarray, pool: np.ndarray, num_wedges: int, lam:
     return est, se, q, u
 
 
+# ---------------------------------------------------------------- Appro-adv (Algorithm 7)
+
+ADV_STREAMS = (8, 9, 10, 11)          # TTT, CCC, TTC, TCC draws
+CLASS_PATTERNS = {"TTT": range(9, 21), "CCC": (1,), "TTC": (6, 7, 8), "TCC": (2, 3, 4, 5)}
+
+
+def adv_split(n_inter: int, n_incl: int, alpha: int):
+    """Algorithm 7, line 4: alpha1 = |T|^2 a / |W|^2, alpha2 = |C|^2 a / |W|^2,
+    alpha3 = alpha4 = |T| |C| a / |W|^2, rounded half up, at least 1 where
+    the lists drawn from are non-empty (0 otherwise)."""
+    w = float(n_inter + n_incl)
+
+    def share(num, ok):
+        if not ok or w <= 0:
+            return 0
+        return max(int(np.floor(num / (w * w) * alpha + 0.5)), 1)
+    a3 = share(float(n_inter) * n_incl, n_inter > 0 and n_incl > 0)
+    return [share(float(n_inter) ** 2, n_inter > 0), share(float(n_incl) ** 2, n_incl > 0), a3, a3]
+
+
+def adv_cross_count(E, rank, x: int, y: int, cpart, cls: str) -> np.ndarray:
+    """Mixed-class hyper-triangles attributed to the hyperwedge {x, y}
+    (normalised ids; E their vertex sets; cpart[z] the hyperedges joined to z
+    by an inclusion hyperwedge).  cls "TTC" (x, y an intersection
+    hyperwedge): the triangles with exactly one inclusion hyperwedge, counted
+    when {x, y} is the earlier of their two intersection hyperwedges; "TCC"
+    (x, y an inclusion hyperwedge): exactly two inclusion hyperwedges,
+    counted when {x, y} is the earlier of the two.  Hyperwedges are ordered
+    by their (smaller rank, larger rank) pairs.  Patterns by the canonical
+    region masks.  Returns int64[21]."""
+    from oracle import brute
+
+    def key(a, b):
+        return tuple(sorted((int(rank[a]), int(rank[b]))))
+    out = np.zeros(21, np.int64)
+    me = key(x, y)
+    for k in sorted((cpart.get(x, set()) | cpart.get(y, set())) - {x, y}):
+        ix, iy = k in cpart.get(x, set()), k in cpart.get(y, set())
+        if ix and iy:
+            continue                           # three inclusion hyperwedges
+        inc_end, other = (x, y) if ix else (y, x)
+        if not (E[other] & E[k]):
+            continue
+        rival = key(other, k) if cls == "TTC" else key(inc_end, k)
+        if me < rival:
+            p = brute.pattern_of(E[x], E[y], E[k])
+            assert p in CLASS_PATTERNS[cls], (cls, p)
+            out[p] += 1
+            out[0] += 1
+    return out
+
+
+def appro_adv(seed: int, alpha: int, t_pos: np.ndarray, c_pos: np.ndarray, close_fwd, cross):
+    """Algorithm 7 with sigma = 1 over the hyperwedge list of some order:
+    t_pos / c_pos the positions of the intersection / inclusion hyperwedges
+    in it (ascending); close_fwd(positions) -> int64[n, 21] forward closures;
+    cross(cls, positions) -> int64[n, 21] mixed-class counts.  Draw t of a
+    list is its element floor(u_t * size / 2^64), u_t from Philox streams
+    8..11.  Returns (est[21], alphas[4])."""
+    nT, nC = int(t_pos.shape[0]), int(c_pos.shape[0])
+    alphas = adv_split(nT, nC, alpha)
+    est = np.zeros(21)
+    jobs = (("TTT", t_pos, alphas[0], ADV_STREAMS[0]), ("CCC", c_pos, alphas[1], ADV_STREAMS[1]),
+            ("TTC", t_pos, alphas[2], ADV_STREAMS[2]), ("TCC", c_pos, alphas[3], ADV_STREAMS[3]))
+    for cls, lst, a, stream in jobs:
+        if a <= 0:
+            continue
+        pos = lst[uniform_indices(seed, stream, a, lst.shape[0])]
+        counts = close_fwd(pos) if cls in ("TTT", "CCC") else cross(cls, pos)
+        tot = counts.sum(axis=0)
+        for p in CLASS_PATTERNS[cls]:
+            est[p] = float(tot[p]) * float(lst.shape[0]) / float(a)
+    est[0] = sum(est[1:].tolist())              # pattern order, left to right
+    return est, alphas
+
+
 def relative_error(est: np.ndarray, exact: np.ndarray):
     """Mean of |H - est| / H over the patterns with H > 0 (the error metric of
     Section 6.3, restricted to patterns that occur), and the per-pattern

@@ -184,6 +184,10 @@ htri_status htri_clear_wedges(htri_graph *h) {
         g.indeg.reset();
         g.inpos.reset();
         g.insnap.reset();
+        g.incl_pos.reset();
+        g.incl_pairs.reset();
+        g.n_incl_pairs = 0;
+        g.have_incl = false;
         g.nw = 0;
         g.have_wedges = false;
     });

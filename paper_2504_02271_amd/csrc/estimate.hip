@@ -50,8 +50,12 @@ htri_status htri_estimate(htri_graph *h, const htri_sample_params *p, double est
         h->g.err = "htri_build_wedges has not run";
         return HTRI_E_STATE;
     }
-    if (p->proposal != 0 && p->proposal != 1) {
-        h->g.err = "proposal must be 0 (uniform) or 1 (learned)";
+    if (p->proposal != 0 && p->proposal != 1 && p->proposal != 2) {
+        h->g.err = "proposal must be 0 (uniform), 1 (learned) or 2 (split by hyperwedge type)";
+        return HTRI_E_INVALID;
+    }
+    if (p->proposal == 2 && (p->flags & HTRI_SAMPLE_EXACT_INCLUSION)) {
+        h->g.err = "the split by hyperwedge type samples the inclusion hyperwedges itself";
         return HTRI_E_INVALID;
     }
     if (p->proposal == 1 && !p->model) {
@@ -83,6 +87,24 @@ htri_status htri_estimate(htri_graph *h, const htri_sample_params *p, double est
         }
         int64_t n = p->num_samples > 0 ? p->num_samples : (int64_t)std::llround(p->budget_fraction * (double)nw);
         if (n < 1) n = 1;
+        if (p->proposal == 2) {
+            hipEvent_t a0, a1;
+            HTRI_HIP(hipEventCreate(&a0));
+            HTRI_HIP(hipEventCreate(&a1));
+            HTRI_HIP(hipEventRecord(a0, s));
+            int64_t alphas[4];
+            adv_estimate(g, n, p->seed, e, se, alphas);
+            HTRI_HIP(hipEventRecord(a1, s));
+            HTRI_HIP(hipEventSynchronize(a1));
+            float ms = 0;
+            HTRI_HIP(hipEventElapsedTime(&ms, a0, a1));
+            (void)hipEventDestroy(a0);
+            (void)hipEventDestroy(a1);
+            std::memcpy(est, e, sizeof(e));
+            if (stderr_) std::memcpy(stderr_, se, sizeof(se));
+            if (time_ms) *time_ms = ms;
+            return;
+        }
         hipEvent_t e0, e1;
         HTRI_HIP(hipEventCreate(&e0));
         HTRI_HIP(hipEventCreate(&e1));
@@ -140,6 +162,12 @@ htri_status htri_estimate(htri_graph *h, const htri_sample_params *p, double est
         if (stderr_) std::memcpy(stderr_, se, sizeof(se));
         if (time_ms) *time_ms = ms;
     });
+}
+
+htri_status htri_adv_split(int64_t n_inter, int64_t n_incl, int64_t alpha, int64_t out[4]) {
+    if (!out || n_inter < 0 || n_incl < 0 || alpha < 0) return HTRI_E_INVALID;
+    adv_split(n_inter, n_incl, alpha, out);
+    return HTRI_OK;
 }
 
 htri_status htri_close_wedges(htri_graph *h, const int64_t *wedge_idx, int64_t n, int64_t *out) {

@@ -172,6 +172,13 @@ struct Graph {
     DBuf<uint32_t> insnap;      // kWindowStarts snapshots of indeg over ranks [insnap_top, m)
     int64_t insnap_top = 0;
     int64_t summary[6] = {0, 0, 0, 0, 0, 0};
+    // inclusion hyperwedges for the class-split sampler (built on first use):
+    // their positions ascending, and (end, other end) pairs of ranks, both
+    // ways, sorted
+    bool have_incl = false;
+    DBuf<int64_t> incl_pos;
+    DBuf<int2> incl_pairs;
+    int64_t n_incl_pairs = 0;
 
     Timings tm;
     int64_t cstats[16] = {0};
@@ -318,6 +325,13 @@ void sample_sums(Graph &g, int mode, int64_t n, uint64_t seed, const int64_t *po
                  bool skip_inclusion = false);
 // positions (forward-adjacency indices) of every inclusion hyperwedge
 int64_t list_inclusion_wedges(Graph &g, DBuf<int64_t> &out);
+// advanced.hip: Appro-adv's draw split (alpha1..alpha4) and its estimate
+void adv_split(int64_t n_inter, int64_t n_incl, int64_t alpha, int64_t out[4]);
+void adv_estimate(Graph &g, int64_t alpha, uint64_t seed, double est[21], double se[21], int64_t alphas[4]);
+// closure sums over draws from one hyperwedge type (advanced.hip's sampler)
+void class_sample_sums(Graph &g, int kind, int64_t n, uint64_t seed, uint32_t stream, const int64_t *inc_pos,
+                       int64_t n_inc, int64_t list_size, uint32_t keep_mask, long long c[21], double y[21],
+                       double y2[21]);
 void draw_pool(Graph &g, uint64_t seed, int64_t pool_n, int64_t *dev_pool);
 void scan_inclusive_f64(Allocator &a, const double *in, double *out, int64_t n, hipStream_t s);
 

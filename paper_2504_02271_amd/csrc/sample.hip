@@ -10,7 +10,6 @@
 // that every floating-point sum has a fixed order.
 #include <algorithm>
 #include <cmath>
-
 #include "internal.hpp"
 #include "philox.hpp"
 
@@ -71,6 +70,16 @@ struct SampleArgs {
     int64_t pool_n;
     double scale;               // multiplies every closure (mode 1: |wedges|; mode 2: |wedges|/pool)
     int skip_inclusion;         // drawn inclusion hyperwedges close nothing (their stratum is exact)
+    // mode 3: draws from one hyperwedge type (Philox stream cls_stream): the
+    // cls_n inclusion hyperwedges at the sorted positions cls_pos (cls_kind
+    // 1), or the intersection ones, every other position (cls_kind 0); only
+    // the patterns in keep_mask are counted
+    const int64_t *cls_pos;
+    int64_t cls_npos;           // number of inclusion positions in cls_pos
+    int64_t cls_n;              // size of the drawn type's list
+    int cls_kind;
+    uint32_t cls_stream;
+    uint32_t keep_mask;
     // accumulation: per wave [21] x (int64 sum c, double sum y, double sum y^2)
     long long *acc_c;
     double *acc_y;
@@ -218,6 +227,20 @@ __global__ __launch_bounds__(kBlock) void k_sample_close(SampleArgs A) {
             e = A.idx[t];
         } else if (MODE == 1) {
             e = (int64_t)philox_index(A.seed, 0u, (uint64_t)t, (uint64_t)A.nw);
+        } else if (MODE == 3) {
+            const int64_t u = (int64_t)philox_index(A.seed, A.cls_stream, (uint64_t)t, (uint64_t)A.cls_n);
+            if (A.cls_kind == 1) {
+                e = A.cls_pos[u];
+            } else {
+                // the u-th position that holds no inclusion hyperwedge: u plus
+                // the number of inclusion positions p_i with p_i - i <= u
+                int64_t lo = 0, hi = A.cls_npos;
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (A.cls_pos[mid] - mid <= u) lo = mid + 1; else hi = mid;
+                }
+                e = u + lo;
+            }
         } else {
             // inverse CDF over the pool: first u with cdf[u] > U * total
             const double total = A.cdf[A.pool_n - 1];
@@ -231,7 +254,8 @@ __global__ __launch_bounds__(kBlock) void k_sample_close(SampleArgs A) {
             e = A.pool ? A.pool[lo] : lo;
             wgt = A.scale / q;
         }
-        const long long c = wave_close(A, lut, e);
+        long long c = wave_close(A, lut, e);
+        if (MODE == 3) c = ((A.keep_mask >> lane) & 1u) ? c : 0;
         if (MODE == 0) {
             if (lane < 21) A.out_counts[t * 21 + lane] = c;
         } else {
@@ -338,6 +362,38 @@ void enumerate_all_wedges(Graph &g, int target, int64_t capacity, int32_t *dev_o
     HTRI_HIP(hipStreamSynchronize(s));
 }
 
+namespace {
+
+// Launch the sampling closure and the fixed-order reduction of its per-wave
+// sums into dc / dy / dy2 (21 each); the per-wave buffers hold
+// grid * kWavesPerBlock * 21 entries.
+void launch_sample_sums(Graph &g, int mode, int grid, int64_t n, uint64_t seed, const int64_t *pool,
+                        const double *cdf, int64_t pool_n, double scale, bool skip_inclusion, const uint8_t *lut,
+                        long long *ac, double *ay, double *ay2, long long *dc, double *dy, double *dy2) {
+    hipStream_t s = g.stream;
+    const int64_t nwaves = (int64_t)grid * kWavesPerBlock;
+    SampleArgs a = base_args(g, lut);
+    a.n = n;
+    a.seed = seed;
+    a.pool = pool;
+    a.cdf = cdf;
+    a.pool_n = pool_n;
+    a.scale = scale;
+    a.skip_inclusion = skip_inclusion ? 1 : 0;
+    a.acc_c = ac;
+    a.acc_y = ay;
+    a.acc_y2 = ay2;
+    if (mode == 1)
+        hipLaunchKernelGGL(k_sample_close<1>, dim3(grid), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_sample_close<2>, dim3(grid), dim3(kBlock), 0, s, a);
+    HTRI_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sample_reduce, dim3(21), dim3(kReduceThreads), 0, s, ac, ay, ay2, nwaves, dc, dy, dy2);
+    HTRI_LAUNCH_CHECK();
+}
+
+}  // namespace
+
 // Weighted closure sums over n draws.  mode 1: uniform (scale = |wedges|);
 // mode 2: from a pool by its CDF (scale = |wedges| / pool size).
 void sample_sums(Graph &g, int mode, int64_t n, uint64_t seed, const int64_t *pool, const double *cdf,
@@ -350,24 +406,48 @@ void sample_sums(Graph &g, int mode, int64_t n, uint64_t seed, const int64_t *po
     const int64_t nwaves = (int64_t)grid * kWavesPerBlock;
     DBuf<long long> ac(A, nwaves * 21);
     DBuf<double> ay(A, nwaves * 21), ay2(A, nwaves * 21);
+    DBuf<long long> dc(A, 21);
+    DBuf<double> dy(A, 21), dy2(A, 21);
+    launch_sample_sums(g, mode, grid, n, seed, pool, cdf, pool_n, scale, skip_inclusion, lut.p, ac.p, ay.p, ay2.p,
+                       dc.p, dy.p, dy2.p);
+    HTRI_HIP(hipMemcpyAsync(c, dc.p, sizeof(long long) * 21, hipMemcpyDeviceToHost, s));
+    HTRI_HIP(hipMemcpyAsync(y, dy.p, sizeof(double) * 21, hipMemcpyDeviceToHost, s));
+    HTRI_HIP(hipMemcpyAsync(y2, dy2.p, sizeof(double) * 21, hipMemcpyDeviceToHost, s));
+    HTRI_HIP(hipStreamSynchronize(s));
+}
+
+// Closure sums over n draws from one hyperwedge type (Appro-adv): kind 1
+// the inclusion list (sorted positions inc_pos, n_inc of them), kind 0 the
+// intersection list (every other position); Philox stream `stream`; only the
+// patterns of keep_mask are summed; every closure weighs list_size.
+void class_sample_sums(Graph &g, int kind, int64_t n, uint64_t seed, uint32_t stream, const int64_t *inc_pos,
+                       int64_t n_inc, int64_t list_size, uint32_t keep_mask, long long c[21], double y[21],
+                       double y2[21]) {
+    hipStream_t s = g.stream;
+    Allocator &A = g.al;
+    DBuf<uint8_t> lut(A, 128);
+    HTRI_HIP(hipMemcpyAsync(lut.p, pattern_lut(), 128, hipMemcpyHostToDevice, s));
+    const int grid = std::max(1, sample_grid());
+    const int64_t nwaves = (int64_t)grid * kWavesPerBlock;
+    DBuf<long long> ac(A, nwaves * 21);
+    DBuf<double> ay(A, nwaves * 21), ay2(A, nwaves * 21);
+    DBuf<long long> dc(A, 21);
+    DBuf<double> dy(A, 21), dy2(A, 21);
     SampleArgs a = base_args(g, lut.p);
     a.n = n;
     a.seed = seed;
-    a.pool = pool;
-    a.cdf = cdf;
-    a.pool_n = pool_n;
-    a.scale = scale;
-    a.skip_inclusion = skip_inclusion ? 1 : 0;
+    a.scale = (double)list_size;
+    a.cls_pos = inc_pos;
+    a.cls_npos = n_inc;
+    a.cls_n = list_size;
+    a.cls_kind = kind;
+    a.cls_stream = stream;
+    a.keep_mask = keep_mask;
     a.acc_c = ac.p;
     a.acc_y = ay.p;
     a.acc_y2 = ay2.p;
-    if (mode == 1)
-        hipLaunchKernelGGL(k_sample_close<1>, dim3(grid), dim3(kBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_sample_close<2>, dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_sample_close<3>, dim3(grid), dim3(kBlock), 0, s, a);
     HTRI_LAUNCH_CHECK();
-    DBuf<long long> dc(A, 21);
-    DBuf<double> dy(A, 21), dy2(A, 21);
     hipLaunchKernelGGL(k_sample_reduce, dim3(21), dim3(kReduceThreads), 0, s, ac.p, ay.p, ay2.p, nwaves, dc.p, dy.p,
                        dy2.p);
     HTRI_LAUNCH_CHECK();

@@ -116,6 +116,7 @@ def load_library() -> ctypes.CDLL:
         "htri_close_wedges": ([_P, _P, _i64, _P], ctypes.c_int),
         "htri_wedge_features": ([_P, _P], ctypes.c_int),
         "htri_proposal_scores": ([_P, _P, _P, _i64, _P], ctypes.c_int),
+        "htri_adv_split": ([_i64, _i64, _i64, _P], ctypes.c_int),
         "htri_model_save": ([_P, ctypes.c_char_p], ctypes.c_int),
         "htri_model_load": ([_P, ctypes.c_char_p], ctypes.c_int),
         "htri_model_last_error": ([_P], ctypes.c_char_p),
@@ -389,6 +390,13 @@ class Graph:
         ms = np.zeros(6, np.float64)
         _check(self._lib.htri_last_timings(self._h, _ptr(ms)), "htri_last_timings", self._h)
         return ms
+
+
+def adv_split(n_inter: int, n_incl: int, alpha: int) -> np.ndarray:
+    """Appro-adv's draws per class: [alpha1 (TTT), alpha2 (CCC), alpha3 (TTC), alpha4 (TCC)]."""
+    out = np.zeros(4, np.int64)
+    _check(load_library().htri_adv_split(int(n_inter), int(n_incl), int(alpha), _ptr(out)), "htri_adv_split")
+    return out
 
 
 def clustering_coefficient(counts, connected_triples: int, epsilon=None) -> float:
