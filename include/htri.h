@@ -312,6 +312,25 @@ htri_status htri_estimate(htri_graph *g, const htri_sample_params *p, double est
  * leaves the rounding open), 0 otherwise.  Host arithmetic only. */
 htri_status htri_adv_split(int64_t n_inter, int64_t n_incl, int64_t alpha, int64_t out[4]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * uniform estimate of htri_estimate (proposal 0, no flags, num_samples
+ * draws under `seed`), computed without any allocation.  Its intermediate
+ * buffers (the pattern table, per-wave partial sums and their reduction,
+ * about 4 MB on 256 compute units) live in one static 8 MiB device array
+ * per GPU, held until the process ends; a device whose sampling grid would
+ * need more is refused with HTRI_E_UNSUPPORTED.  Calls that overlap on one
+ * GPU share that array and race: issue them one after another (one stream,
+ * or synchronised).  Work is only enqueued on the handle's stream; nothing
+ * is synchronised.
+ *   dev_est     device double[21]: the estimate (bit-identical to
+ *               htri_estimate's est for the same draws).
+ *   dev_stderr  NULL or device double[21]: the standard errors.
+ * Errors: HTRI_E_INVALID (NULL, num_samples < 1), HTRI_E_STATE (no
+ * hyperwedges yet), HTRI_E_UNSUPPORTED, HTRI_E_DEVICE. */
+htri_status htri_estimate_uniform_noalloc(htri_graph *g, int64_t num_samples, uint64_t seed, double *dev_est,
+                                          double *dev_stderr);
+
 /* Sub-hypergraph for sigma-sampling (Algorithm 6, with sigma in (0, 1]: the
  * hyperedges are subsampled before the hyperwedges are, and the estimate is
  * scaled back; Section 4.2).  Hyperedge x of g (normalised id) gets the

@@ -10,6 +10,10 @@
 // that every floating-point sum has a fixed order.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+
 #include "internal.hpp"
 #include "philox.hpp"
 
@@ -465,3 +469,118 @@ void draw_pool(Graph &g, uint64_t seed, int64_t pool_n, int64_t *dev_pool) {
 }
 
 }  // namespace htri
+
+// ---------------------------------------------------------------- no-allocation uniform estimate
+//
+// htri_estimate_uniform_noalloc keeps every intermediate buffer of the
+// uniform estimate (the pattern table, the per-wave partial sums and their
+// reduction) in one file-scope device array instead of allocating.  The
+// host code never passes the array's name to a kernel: it looks the array's
+// device address up once per device (hipGetSymbolAddress) and passes that.
+
+namespace htri {
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)8 << 20;
+constexpr size_t kScratchLutOff = 0;          // 128 B pattern table
+constexpr size_t kScratchSumOff = 256;        // 21 x (int64 c, double y, double y2)
+constexpr size_t kScratchWaveOff = 4096;      // per-wave sums, 3 x nwaves x 21 x 8 B
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (looked up once per device)
+unsigned char *scratch_on_device() {
+    int dev = 0;
+    HTRI_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) fail(HTRI_E_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HTRI_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) fail(HTRI_E_DEVICE, "no device address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    return (unsigned char *)g_scratch_ptr[dev];
+}
+
+struct LutArg {
+    uint8_t v[128];
+};
+
+__global__ void k_put_lut(LutArg t, uint8_t *dst) {
+    if (threadIdx.x < 128) dst[threadIdx.x] = t.v[threadIdx.x];
+}
+
+// est_q = c_q |wedges| / n and its standard error, as htri_estimate forms them
+__global__ void k_uniform_finish(const long long *c, const double *y, const double *y2, int64_t n, int64_t nw,
+                                 double *est, double *se) {
+    const int q = threadIdx.x;
+    if (q >= 21) return;
+    if (n <= 0 || nw <= 0) {
+        est[q] = 0.0;
+        if (se) se[q] = 0.0;
+        return;
+    }
+    const double e = (double)c[q] * (double)nw / (double)n;
+    est[q] = e;
+    if (se) {
+        const double nn = (double)n, ne = nn * e;
+        const double var = (y2[q] - ne * e) / (nn * (double)(n > 1 ? n - 1 : 1));
+        se[q] = sqrt(var > 0.0 ? var : 0.0);
+    }
+}
+
+}  // namespace
+
+}  // namespace htri
+
+using namespace htri;
+
+extern "C" htri_status htri_estimate_uniform_noalloc(htri_graph *h, int64_t num_samples, uint64_t seed,
+                                                     double *dev_est, double *dev_stderr) {
+    if (!h || !dev_est || num_samples < 1) return HTRI_E_INVALID;
+    if (!h->g.have_wedges) {
+        h->g.err = "htri_build_wedges has not run";
+        return HTRI_E_STATE;
+    }
+    try {
+        Graph &g = h->g;
+        hipStream_t s = g.stream;
+        unsigned char *base = scratch_on_device();
+        const int grid = std::max(1, sample_grid());
+        const int64_t nwaves = (int64_t)grid * kWavesPerBlock;
+        const size_t need = kScratchWaveOff + (size_t)3 * (size_t)nwaves * 21 * 8;
+        if (need > kScratchBytes) {
+            g.err = "this device needs " + std::to_string(need) + " bytes of sampling scratch; the static buffer holds " +
+                    std::to_string(kScratchBytes);
+            return HTRI_E_UNSUPPORTED;
+        }
+        uint8_t *lut = base + kScratchLutOff;
+        long long *dc = (long long *)(base + kScratchSumOff);
+        double *dy = (double *)(base + kScratchSumOff + 21 * 8);
+        double *dy2 = (double *)(base + kScratchSumOff + 42 * 8);
+        long long *ac = (long long *)(base + kScratchWaveOff);
+        double *ay = (double *)(base + kScratchWaveOff + (size_t)nwaves * 21 * 8);
+        double *ay2 = (double *)(base + kScratchWaveOff + (size_t)2 * nwaves * 21 * 8);
+        if (g.nw > 0) {
+            LutArg t;
+            std::memcpy(t.v, pattern_lut(), 128);
+            hipLaunchKernelGGL(k_put_lut, dim3(1), dim3(128), 0, s, t, lut);
+            HTRI_LAUNCH_CHECK();
+            // every wave writes its own partial sums, so nothing needs clearing
+            launch_sample_sums(g, 1, grid, num_samples, seed, nullptr, nullptr, 0, (double)g.nw, false, lut, ac, ay,
+                               ay2, dc, dy, dy2);
+        }
+        hipLaunchKernelGGL(k_uniform_finish, dim3(1), dim3(64), 0, s, dc, dy, dy2, g.nw > 0 ? num_samples : 0, g.nw,
+                           dev_est, dev_stderr);
+        HTRI_LAUNCH_CHECK();
+        return HTRI_OK;
+    } catch (const htri::Error &e) {
+        h->g.err = e.msg;
+        return e.code;
+    }
+}

@@ -116,6 +116,7 @@ def load_library() -> ctypes.CDLL:
         "htri_close_wedges": ([_P, _P, _i64, _P], ctypes.c_int),
         "htri_wedge_features": ([_P, _P], ctypes.c_int),
         "htri_proposal_scores": ([_P, _P, _P, _i64, _P], ctypes.c_int),
+        "htri_estimate_uniform_noalloc": ([_P, _i64, _u64, _P, _P], ctypes.c_int),
         "htri_adv_split": ([_i64, _i64, _i64, _P], ctypes.c_int),
         "htri_model_save": ([_P, ctypes.c_char_p], ctypes.c_int),
         "htri_model_load": ([_P, ctypes.c_char_p], ctypes.c_int),
@@ -352,6 +353,21 @@ class Graph:
         _check(self._lib.htri_estimate(self._h, ctypes.byref(p), _ptr(est), _ptr(se), ctypes.byref(ms)),
                "htri_estimate", self._h)
         return est, se, float(ms.value)
+
+    def estimate_uniform_noalloc(self, num_samples: int, seed: int = 0, est=None, stderr=None):
+        """The uniform estimate computed without device allocation by the
+        library, into caller tensors (float64[21] on the GPU; created here
+        when not given).  Only enqueued on the handle's stream."""
+        import torch
+        if est is None:
+            est = torch.zeros(21, dtype=torch.float64, device="cuda")
+        if stderr is None:
+            stderr = torch.zeros(21, dtype=torch.float64, device="cuda")
+        _check(self._lib.htri_estimate_uniform_noalloc(self._h, int(num_samples), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                                       ctypes.c_void_p(est.data_ptr()),
+                                                       ctypes.c_void_p(stderr.data_ptr())),
+               "htri_estimate_uniform_noalloc", self._h)
+        return est, stderr
 
     def close_wedges(self, idx) -> np.ndarray:
         """Per-pattern closure counts int64[n, 21] of the listed wedges (get_wedges order)."""
