@@ -105,6 +105,10 @@ typedef struct {
 #define HTRI_COUNT_OWNER_PROBE 128u  /* probe every partner's whole forward    */
                                      /* list against its owner's (instead of   */
                                      /* each owner's rest against the middle)  */
+/* Class-targeted counts of the intersection-only class (Section 3.2): */
+#define HTRI_COUNT_DENSE_TTT 512u    /* patterns 9-16 only (DenseTTT)          */
+#define HTRI_COUNT_COMMON_VERTEX 1024u /* pattern 9 only                       */
+#define HTRI_COUNT_SPARSE_TTT 2048u  /* patterns 17-20 only (SparseTTT)        */
 
 /* Load and normalise a hypergraph (Def. 2.1 and the distinct-hyperedge
  * assumption of Section 2), build E_v (Algorithm 2).
@@ -172,7 +176,21 @@ htri_status htri_get_wedge_list(const htri_graph *g, const int64_t *wedge_idx, i
  *               come after dst in prec (all patterns).
  *   out_flags   HTRI_OUTPUT_ON_DEVICE, HTRI_COUNT_OWNER_PROBE, and at
  *               most one of HTRI_COUNT_NO_WINDOW / HTRI_COUNT_WINDOW_ALWAYS /
- *               HTRI_COUNT_INCLUSION_CLASSES.  The last counts only the
+ *               HTRI_COUNT_INCLUSION_CLASSES / HTRI_COUNT_DENSE_TTT /
+ *               HTRI_COUNT_COMMON_VERTEX / HTRI_COUNT_SPARSE_TTT.
+ *               DENSE_TTT counts patterns 9-16 without closing every
+ *               hyperwedge (Count-DenseTTT, Section 3.2, Lemma 3.1): pattern
+ *               9 for each vertex v from the hyperedges of size >= 2 holding
+ *               v and the "thick" pairs among them (sharing v and more),
+ *               by inclusion-exclusion over the triples; patterns 10-16,
+ *               which all have a thick pair, by scanning E_v from every
+ *               thick hyperwedge.  COMMON_VERTEX counts pattern 9 alone
+ *               that way.  Both need per_edge and per_wedge NULL; counts[p]
+ *               outside the class are 0.  SPARSE_TTT counts patterns 17-20
+ *               (Count-SparseTTT: the closure with every hit that has a
+ *               vertex common to all three hyperedges dropped as soon as
+ *               g > 0 is known, no dense window); per_edge counts the
+ *               masked patterns among 17-20, per_wedge must be NULL.  The last counts only the
  *               classes whose hyper-triangles hold an inclusion hyperwedge
  *               (patterns 1-8; Count-CCC, Count-TCC and Count-TTC of
  *               Section 3.1 search only around those hyperwedges): counts[p]
@@ -371,6 +389,20 @@ htri_status htri_close_wedges(htri_graph *g, const int64_t *wedge_idx, int64_t n
 htri_status htri_proposal_scores(htri_graph *g, const htri_model *model, const int64_t *wedge_idx, int64_t n,
                                  double *out);
 
+/* Training target of the learned proposal for every hyperwedge (device
+ * float[|wedges|], htri_get_wedges order): log1p(u(w)),
+ *   u(w) = sqrt(sum_p (c_p(w) |wedges| / H_p)^2) / n,
+ * over the n patterns p with H_p = counts[p] > 0, c_p(w) the forward
+ * closure of w in pattern p.  Drawing w in proportion to u(w) minimises
+ * sum_p Var(est_p) / H_p^2 (Cauchy-Schwarz), the squared form of the mean
+ * per-pattern relative error.  flags HTRI_IMPORTANCE_TOTAL adds the total
+ * (counts[0], c_0(w) the whole closure) as one more term, which keeps the
+ * variance of the total -- and of the pattern that dominates it -- in the
+ * objective.  Errors: HTRI_E_INVALID, HTRI_E_STATE, HTRI_E_OOM,
+ * HTRI_E_DEVICE. */
+#define HTRI_IMPORTANCE_TOTAL 1u
+htri_status htri_wedge_importance(htri_graph *g, const int64_t counts[21], uint32_t flags, float *dev_out);
+
 /* Per-wedge proposal features (16 float32 per wedge, htri_get_wedges order)
  * into a device array float[|wedges|*16]. */
 htri_status htri_wedge_features(htri_graph *g, float *dev_features);
@@ -446,6 +478,39 @@ htri_status htri_batch_autotune(htri_batch *b, int32_t repeats, htri_schedule *b
  * to back on the batch's stream; time_ms covers all launches. */
 htri_status htri_batch_count_per_graph(htri_batch *b, const htri_schedule *sched, int64_t *counts,
                                        double *time_ms);
+/* Schedules per size class.  A graph's class is its hyperwedge count:
+ * class 0 below 2^18, class 1 below 2^21, class 2 from 2^21 (written to
+ * class_of_graph, int32[count], by htri_batch_size_classes).
+ * htri_batch_autotune_classes times every schedule on the graphs of each
+ * class (graph-replayed, best of `repeats`) and returns the fastest per
+ * class in best[3] (classes without graphs get 512/256/1 and 0 ms);
+ * cache_path (NULL: none) names a JSON file: when it holds schedules for
+ * this device's architecture and compute-unit count and every populated
+ * class, they are returned without timing (*from_cache = 1), else the
+ * tuned ones are written to it.  htri_batch_count_classes counts every
+ * graph with its class's schedule: one persistent launch per populated
+ * class, all captured in one HIP graph when use_graph != 0.
+ * Errors: HTRI_E_INVALID (also an unwritable cache), HTRI_E_DEVICE. */
+htri_status htri_batch_size_classes(const htri_batch *b, int32_t *class_of_graph);
+htri_status htri_batch_autotune_classes(htri_batch *b, int32_t repeats, const char *cache_path, htri_schedule *best,
+                                        double *best_ms, int32_t *from_cache);
+htri_status htri_batch_count_classes(htri_batch *b, const htri_schedule *sched, int32_t use_graph, int64_t *counts,
+                                     double *time_ms);
+
+/* The whole hot path of every graph -- step 1 (hyperwedges), the closure
+ * work items and the closure -- in ONE captured HIP graph, replayed: each
+ * replay rebuilds every graph's hyperwedges from its loaded hypergraph and
+ * counts all of them.  The first call with a schedule records the per-graph
+ * host code once (its readbacks and allocation sizes), then captures it
+ * with every buffer taken from one device arena the batch keeps (about the
+ * step-1 working memory of all graphs together); later calls only replay.
+ * counts: int64[count][21]; time_ms: device time of the replay. */
+htri_status htri_batch_count_full(htri_batch *b, const htri_schedule *sched, int64_t *counts, double *time_ms);
+/* Baseline for the above: step 1, work items and closure issued graph by
+ * graph from the host, as a caller without the batch would (one launch
+ * sequence per graph, its readbacks included); time_ms is wall time. */
+htri_status htri_batch_count_full_per_graph(htri_batch *b, const htri_schedule *sched, int64_t *counts,
+                                            double *time_ms);
 const char *htri_batch_last_error(const htri_batch *b);
 void htri_batch_free(htri_batch *b); /* NULL-safe */
 

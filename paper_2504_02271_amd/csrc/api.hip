@@ -332,14 +332,16 @@ htri_status htri_get_wedge_list(const htri_graph *hc, const int64_t *wedge_idx, 
 htri_status htri_count_patterns(htri_graph *h, uint32_t per_edge_pattern_mask, int64_t counts[21],
                                 int64_t *per_edge, int32_t *per_wedge, uint32_t out_flags) {
     if (!h || !counts) return HTRI_E_INVALID;
-    if (out_flags & ~(HTRI_OUTPUT_ON_DEVICE | HTRI_COUNT_NO_WINDOW | HTRI_COUNT_WINDOW_ALWAYS |
-                      HTRI_COUNT_INCLUSION_CLASSES | HTRI_COUNT_OWNER_PROBE))
-        return HTRI_E_INVALID;
+    constexpr uint32_t kModes = HTRI_COUNT_NO_WINDOW | HTRI_COUNT_WINDOW_ALWAYS | HTRI_COUNT_INCLUSION_CLASSES |
+                                HTRI_COUNT_DENSE_TTT | HTRI_COUNT_COMMON_VERTEX | HTRI_COUNT_SPARSE_TTT;
+    if (out_flags & ~(HTRI_OUTPUT_ON_DEVICE | HTRI_COUNT_OWNER_PROBE | kModes)) return HTRI_E_INVALID;
     {
-        const uint32_t modes = out_flags & (HTRI_COUNT_NO_WINDOW | HTRI_COUNT_WINDOW_ALWAYS | HTRI_COUNT_INCLUSION_CLASSES);
+        const uint32_t modes = out_flags & kModes;
         if (modes & (modes - 1)) return HTRI_E_INVALID;        // at most one mode
     }
-    if ((out_flags & HTRI_COUNT_INCLUSION_CLASSES) && per_wedge) return HTRI_E_INVALID;
+    if ((out_flags & (HTRI_COUNT_INCLUSION_CLASSES | HTRI_COUNT_SPARSE_TTT)) && per_wedge) return HTRI_E_INVALID;
+    if ((out_flags & (HTRI_COUNT_DENSE_TTT | HTRI_COUNT_COMMON_VERTEX)) && (per_edge || per_wedge))
+        return HTRI_E_INVALID;
     if (!h->g.have_wedges) {
         h->g.err = "htri_build_wedges has not run";
         return HTRI_E_STATE;
@@ -361,8 +363,16 @@ htri_status htri_count_patterns(htri_graph *h, uint32_t per_edge_pattern_mask, i
             else { cw_tmp.alloc(g.al, g.nw); cw_dev = cw_tmp.p; }
         }
         int64_t c[21];
-        if (out_flags & HTRI_COUNT_INCLUSION_CLASSES) htri::count_inclusion_classes(g, mask, c, t_dev);
-        else htri::count_patterns(g, mask, out_flags, c, t_dev, cw_dev);
+        if (out_flags & HTRI_COUNT_INCLUSION_CLASSES) {
+            htri::count_inclusion_classes(g, mask, c, t_dev);
+        } else if (out_flags & (HTRI_COUNT_DENSE_TTT | HTRI_COUNT_COMMON_VERTEX)) {
+            float ms = 0;
+            htri::count_dense_ttt(g, (out_flags & HTRI_COUNT_DENSE_TTT) != 0, c, &ms);
+            g.tm = htri::Timings{};
+            g.tm.closure_ms = ms;
+        } else {
+            htri::count_patterns(g, mask, out_flags, c, t_dev, cw_dev);
+        }
         if (per_edge && !dev && g.m)
             HTRI_HIP(hipMemcpyAsync(per_edge, t_dev, sizeof(int64_t) * g.m, hipMemcpyDeviceToHost, g.stream));
         if (per_wedge && !dev && g.nw)

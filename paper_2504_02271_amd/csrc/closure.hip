@@ -5,17 +5,29 @@
 //
 // Orientation: hyperedges are ranked by prec; the forward list N+(r) holds
 // the later neighbours of r, sorted.  A triangle r < j < k is found exactly
-// once, by owner r, as a k that lies in both N+(r) and N+(j).
+// once, at its two earliest hyperedges: k lies in both N+(r) and N+(j).
 //
-// Work decomposition (MI355X): an item is (owner r, a chunk of at most CAP
-// consecutive entries of N+(r), a piece of at most 256 partners j of r).
-// The chunk goes into an LDS open-addressing hash; every partner's N+(j),
-// restricted to the chunk's rank range, is streamed from HBM with coalesced
-// loads and probed against the hash.  A hit is classified from the sizes,
-// the three omegas and g = popcount(Omega_rj & Omega_rk) (both masks are
-// over e_r's member positions) through a 128-entry region-emptiness table.
-// Persistent blocks pull items from a queue; pattern counts stay in per-lane
-// LDS counters and leave the kernel as one partial per block.
+// Two closures share the owners:
+//  * the dense window (k_window_rows, k_close_window): the owners of the top
+//    ranks get bitmap rows over the window; c(r, j) = |N+(r) & N+(j)| is an
+//    AND + popcount, and the common-vertex pattern is counted in bulk per
+//    (owner, shared vertex) class;
+//  * probing (k_close) for the other owners, by default around the middle
+//    hyperedge: an item is (middle j, a chunk of at most CAP entries of
+//    N+(j), a piece of j's in-list); the chunk goes into an LDS
+//    open-addressing hash and, for every hyperwedge (r, j) of the piece, the
+//    entries of N+(r) after j are streamed from HBM with coalesced loads and
+//    probed against it (HTRI_COUNT_OWNER_PROBE hashes the owner's chunk and
+//    streams each partner's N+(j) instead).
+// A hit is classified from the sizes, the three omegas and g =
+// popcount(Omega & Omega) over the hashed hyperedge's member positions
+// through a 128-entry region-emptiness table (the common-vertex pattern by a
+// shortcut test).  Persistent blocks pull items from two queues (block items,
+// then single-middle wave items).  Pattern counts live one per lane (lane p
+// holds pattern p) and are added to the global counts once per wave when
+// the wave moves to another graph or finishes; per-hyperedge counts come
+// from per-wedge role counters and per-wave sums added to the hyperedges'
+// totals during the closure.
 #include <algorithm>
 
 #include "internal.hpp"
@@ -265,6 +277,9 @@ __device__ __forceinline__ void probe_tile(const uint2 *tab, int hbits, int wbit
     uint2 sm[U];
 #pragma unroll
     for (int u = 0; u < U; u++) sm[u] = ent_sm[hit[u] ? sl[u].y : 0u];
+    // SparseTTT-only counting (emask bit 31): a triangle with a vertex common
+    // to all three hyperedges is dropped as soon as g > 0 is known
+    const bool sparse_only = (emask >> 31) & 1u;
     bool fast[U];
     bool slow = false;
     uint32_t n9 = 0;
@@ -273,6 +288,10 @@ __device__ __forceinline__ void probe_tile(const uint2 *tab, int hbits, int wbit
         const int wik = (int)(sl[u].x & wmask), wjk = (int)(e[u] & wmask);
         fast[u] = hit[u] & ffast[u] & (wik == fwij[u]) & (wjk == fwij[u]) & (sm[u].y == fm0[u]) &
                   ((int)sm[u].x > fwij[u]);
+        if (sparse_only && fast[u]) {
+            hit[u] = false;
+            fast[u] = false;
+        }
         n9 += fast[u];
         po[u] = 0u;
         slow |= hit[u] & !fast[u];
@@ -295,6 +314,10 @@ __device__ __forceinline__ void probe_tile(const uint2 *tab, int hbits, int wbit
                     }
                 } else {
                     g = triple_common(G.eptr, G.emem, r, J.jr, (int32_t)(e[u] >> wbits));
+                }
+                if (sparse_only && g > 0) {
+                    hit[u] = false;
+                    continue;
                 }
                 const uint32_t m7 = region_mask(si, J.sj, (int)sm[u].x, J.wij, wik, wjk, g);
                 if (m7 != kMaskCommonVertex) po[u] = lut[m7];
@@ -1367,9 +1390,8 @@ void items_from_counts(Graph &g, DBuf<int64_t> &icnt, DBuf<int64_t> &wcnt, ItemL
     scan_exclusive_i64(A, icnt.p, icnt.p, m, icnt.p + m, s);
     scan_exclusive_i64(A, wcnt.p, wcnt.p, m, wcnt.p + m, s);
     int64_t tot[2] = {0, 0};
-    HTRI_HIP(hipMemcpyAsync(&tot[0], icnt.p + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HTRI_HIP(hipMemcpyAsync(&tot[1], wcnt.p + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HTRI_HIP(hipStreamSynchronize(s));
+    tot[0] = host_read(icnt.p + m, s);
+    tot[1] = host_read(wcnt.p + m, s);
     out.nblock = tot[0];
     out.nwave = tot[1];
     // the item counters are 32-bit and run past the end by one claim per block or wave
@@ -1378,7 +1400,7 @@ void items_from_counts(Graph &g, DBuf<int64_t> &icnt, DBuf<int64_t> &wcnt, ItemL
     out.block.alloc(A, out.nblock);
     out.wave.alloc(A, out.nwave);
     if (m > 0 && out.nblock + out.nwave > 0) fill();
-    HTRI_HIP(hipStreamSynchronize(s));
+    stream_sync(s);
 }
 
 }  // namespace
@@ -1853,7 +1875,7 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
 WindowPlan choose_window(Graph &g, uint32_t flags) {
     WindowPlan w;
     w.w0 = g.m;
-    if ((flags & HTRI_COUNT_NO_WINDOW) || g.m < 3 || g.nw == 0) return w;
+    if ((flags & (HTRI_COUNT_NO_WINDOW | HTRI_COUNT_SPARSE_TTT)) || g.m < 3 || g.nw == 0) return w;
     auto fptr_at = [&](int64_t i) {
         int64_t v = 0;
         HTRI_HIP(hipMemcpyAsync(&v, g.fptr.p + i, sizeof(int64_t), hipMemcpyDeviceToHost, g.stream));
@@ -2343,7 +2365,9 @@ void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21],
     a.nwitems = items.nwave;
     a.wqueue = (unsigned int *)(ctr.p + 23);
     a.graphs = desc.p;
-    a.emask = mask;
+    // SparseTTT-only counting: bit 31 tells the probe to drop every hit with
+    // a vertex common to all three hyperedges
+    a.emask = (flags & HTRI_COUNT_SPARSE_TTT) ? ((mask & 0x1E0000u) | 0x80000000u) : mask;
     a.lut = lut.p;
     a.cwj = cw_dev;
     a.cwjm = cwjm.p;

@@ -224,6 +224,30 @@ htri_status htri_proposal_scores(htri_graph *h, const htri_model *model, const i
     });
 }
 
+htri_status htri_wedge_importance(htri_graph *h, const int64_t counts[21], uint32_t flags, float *dev_out) {
+    if (!h || !counts || !dev_out || (flags & ~HTRI_IMPORTANCE_TOTAL)) return HTRI_E_INVALID;
+    if (!h->g.have_wedges) {
+        h->g.err = "htri_build_wedges has not run";
+        return HTRI_E_STATE;
+    }
+    return run_g(h, [&] {
+        Graph &g = h->g;
+        double scale[21] = {0};
+        double live = 0;
+        for (int p = 1; p <= 20; p++)
+            if (counts[p] > 0) {
+                scale[p] = (double)g.nw / (double)counts[p];
+                live += 1;
+            }
+        if ((flags & HTRI_IMPORTANCE_TOTAL) && counts[0] > 0) {
+            scale[0] = (double)g.nw / (double)counts[0];
+            live += 1;
+        }
+        if (live == 0) live = 1;
+        wedge_importance_all(g, scale, live, dev_out);
+    });
+}
+
 htri_status htri_wedge_features(htri_graph *h, float *dev_features) {
     if (!h || !dev_features) return HTRI_E_INVALID;
     if (!h->g.have_wedges) {

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "htri.h"
@@ -31,14 +32,104 @@ struct Error {
 
 inline void fail(htri_status code, const std::string &msg) { throw Error{code, msg}; }
 
+// A data-dependent launch sequence (step 1 and the work items of a graph)
+// replayed from a captured HIP graph.  The sequence first runs eagerly in
+// record mode, which keeps every value the host reads back from the device
+// and adds up every allocation; in capture mode the same host code takes
+// those values from the record (no device-to-host copy, no stream
+// synchronisation: the stream is being captured) and its buffers from one
+// arena that is never reused, so every captured kernel keeps its buffers.
+// Host arrays that captured copies read are kept in the record too.
+struct Replay {
+    enum Mode { kRecord, kCapture } mode = kRecord;
+    std::vector<int64_t> vals;          // host readbacks, in order
+    size_t next = 0;
+    std::vector<std::vector<uint8_t>> host_srcs;
+    size_t arena_bytes = 0;             // record: sum of the (aligned) allocations
+    char *arena = nullptr;
+    size_t arena_size = 0, arena_off = 0;
+    bool capturing() const { return mode == kCapture; }
+};
+// the replay the calling thread is recording or capturing (nullptr: none)
+extern thread_local Replay *tl_replay;
+
+inline bool replay_capturing() { return tl_replay && tl_replay->mode == Replay::kCapture; }
+
+// stream synchronisation, skipped while a replay is being captured
+inline void stream_sync(hipStream_t s) {
+    if (replay_capturing()) return;
+    HTRI_HIP(hipStreamSynchronize(s));
+}
+
+// n 64-bit values read back from the device (recorded, or replayed)
+inline void host_read_words(const void *dev, int64_t n, void *host, hipStream_t s) {
+    if (n <= 0) return;
+    if (replay_capturing()) {
+        Replay &r = *tl_replay;
+        if (r.next + (size_t)n > r.vals.size()) fail(HTRI_E_STATE, "replay ran past its recorded values");
+        std::memcpy(host, r.vals.data() + r.next, sizeof(int64_t) * (size_t)n);
+        r.next += (size_t)n;
+        return;
+    }
+    HTRI_HIP(hipMemcpyAsync(host, dev, sizeof(int64_t) * (size_t)n, hipMemcpyDeviceToHost, s));
+    HTRI_HIP(hipStreamSynchronize(s));
+    if (tl_replay) {
+        const int64_t *h = (const int64_t *)host;
+        tl_replay->vals.insert(tl_replay->vals.end(), h, h + n);
+    }
+}
+
+template <typename T>
+T host_read(const T *dev, hipStream_t s) {
+    static_assert(sizeof(T) <= 8, "one word");
+    int64_t w = 0;
+    if (replay_capturing()) {
+        host_read_words(dev, 1, &w, s);
+    } else {
+        T h{};
+        HTRI_HIP(hipMemcpyAsync(&h, dev, sizeof(T), hipMemcpyDeviceToHost, s));
+        HTRI_HIP(hipStreamSynchronize(s));
+        std::memcpy(&w, &h, sizeof(T));
+        if (tl_replay) tl_replay->vals.push_back(w);
+    }
+    T out{};
+    std::memcpy(&out, &w, sizeof(T));
+    return out;
+}
+
+// host data a captured host-to-device copy reads at every replay: kept in
+// the record while capturing
+inline const void *persist_host(const void *p, size_t bytes) {
+    if (!replay_capturing() || bytes == 0) return p;
+    tl_replay->host_srcs.emplace_back((const uint8_t *)p, (const uint8_t *)p + bytes);
+    return tl_replay->host_srcs.back().data();
+}
+
 // Device memory through the caller's allocator (or hipMallocAsync/hipMalloc).
 struct Allocator {
     htri_allocator user{};
     bool has_user = false;
     hipStream_t stream = nullptr;
+    // replay arenas whose pieces this allocator handed out while capturing;
+    // releasing them is a no-op (each arena's owner frees it whole)
+    std::vector<std::pair<const char *, const char *>> arenas;
+    bool in_arena(const void *p) const {
+        for (const auto &a : arenas)
+            if ((const char *)p >= a.first && (const char *)p < a.second) return true;
+        return false;
+    }
 
     void *alloc(size_t bytes) {
         if (bytes == 0) bytes = 256;
+        const size_t aligned = (bytes + 255) & ~(size_t)255;
+        if (replay_capturing()) {
+            Replay &r = *tl_replay;
+            if (r.arena_off + aligned > r.arena_size) fail(HTRI_E_STATE, "replay arena exhausted");
+            void *q = r.arena + r.arena_off;
+            r.arena_off += aligned;
+            return q;
+        }
+        if (tl_replay) tl_replay->arena_bytes += aligned;
         void *p = nullptr;
         if (has_user) {
             p = user.alloc(bytes, (void *)stream, user.ctx);
@@ -54,6 +145,7 @@ struct Allocator {
     }
     void release(void *p) {
         if (!p) return;
+        if (!arenas.empty() && in_arena(p)) return;   // owned by a replay arena
         if (has_user)
             user.free(p, (void *)stream, user.ctx);
         else
@@ -154,6 +246,10 @@ struct Graph {
     DBuf<int64_t> vptr;         // E_v lists, ascending rank
     DBuf<int32_t> vadj;
     DBuf<int32_t> vpos;         // membership -> its position inside E_v
+
+    // a graph of a batch: counted by probing around the owner only, so step 1
+    // keeps no in-list slots and no per-window-start snapshots
+    bool batch_member = false;
 
     // step 1: forward adjacency N+(r), sorted by rank
     bool have_wedges = false;
@@ -325,6 +421,10 @@ void sample_sums(Graph &g, int mode, int64_t n, uint64_t seed, const int64_t *po
                  bool skip_inclusion = false);
 // positions (forward-adjacency indices) of every inclusion hyperwedge
 int64_t list_inclusion_wedges(Graph &g, DBuf<int64_t> &out);
+// sample.hip: the learned proposal's training target of every hyperwedge
+void wedge_importance_all(Graph &g, const double scale[21], double live, float *dev_out);
+// dense.hip: DenseTTT counts (patterns 9-16, or 9 alone) into counts[21]
+void count_dense_ttt(Graph &g, bool rest, int64_t counts[21], float *ms);
 // advanced.hip: Appro-adv's draw split (alpha1..alpha4) and its estimate
 void adv_split(int64_t n_inter, int64_t n_incl, int64_t alpha, int64_t out[4]);
 void adv_estimate(Graph &g, int64_t alpha, uint64_t seed, double est[21], double se[21], int64_t alphas[4]);

@@ -265,7 +265,7 @@ void radix_sort_u64(Allocator &a, uint64_t *keys, uint32_t *vals, int64_t n, int
         if (vals) HTRI_HIP(hipMemcpyAsync(vals, vin, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
     }
     // the temporaries are released when this returns; keep the stream ordered
-    HTRI_HIP(hipStreamSynchronize(s));
+    stream_sync(s);
 }
 
 void fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s) {
@@ -279,6 +279,8 @@ void fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill<uint64_t>, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, n, v);
     HTRI_LAUNCH_CHECK();
 }
+
+thread_local Replay *tl_replay = nullptr;
 
 int device_cu_count() {
     int dev = 0, cus = 0;

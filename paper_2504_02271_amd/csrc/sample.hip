@@ -312,6 +312,30 @@ __global__ __launch_bounds__(kReduceThreads) void k_sample_reduce(const long lon
     }
 }
 
+// Training target of the learned proposal for every hyperwedge e:
+// log1p(sqrt(sum_p (c_p(e) * scale[p])^2) / live), c_p(e) the forward closure
+// of e in pattern p, scale[p] = |wedges| / H_p for the patterns present (0
+// otherwise); scale[0] weighs the total closure (0: left out).  One wave per
+// hyperwedge.
+__global__ __launch_bounds__(kBlock) void k_wedge_importance(SampleArgs A, const double *scale, double live,
+                                                             float *out) {
+    __shared__ uint8_t lut[128];
+    if (threadIdx.x < 128) lut[threadIdx.x] = A.lut[threadIdx.x];
+    __syncthreads();
+    const int lane = __lane_id();
+    const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    const double sc = lane < 21 ? scale[lane] : 0.0;
+    for (int64_t e = wave; e < A.nw; e += nwaves) {
+        const long long c = wave_close(A, lut, e);
+        double y = (double)c * sc;
+        y = y * y;
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) y += __shfl_xor(y, o, kWave);
+        if (lane == 0) out[e] = (float)log1p(sqrt(y) / live);
+    }
+}
+
 __global__ void k_pool_draw(uint64_t seed, int64_t pool_n, int64_t nw, int64_t *pool) {
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < pool_n;
          u += (int64_t)gridDim.x * blockDim.x)
@@ -417,6 +441,20 @@ void sample_sums(Graph &g, int mode, int64_t n, uint64_t seed, const int64_t *po
     HTRI_HIP(hipMemcpyAsync(c, dc.p, sizeof(long long) * 21, hipMemcpyDeviceToHost, s));
     HTRI_HIP(hipMemcpyAsync(y, dy.p, sizeof(double) * 21, hipMemcpyDeviceToHost, s));
     HTRI_HIP(hipMemcpyAsync(y2, dy2.p, sizeof(double) * 21, hipMemcpyDeviceToHost, s));
+    HTRI_HIP(hipStreamSynchronize(s));
+}
+
+void wedge_importance_all(Graph &g, const double scale[21], double live, float *dev_out) {
+    if (g.nw <= 0) return;
+    hipStream_t s = g.stream;
+    DBuf<uint8_t> lut(g.al, 128);
+    HTRI_HIP(hipMemcpyAsync(lut.p, pattern_lut(), 128, hipMemcpyHostToDevice, s));
+    DBuf<double> sc(g.al, 21);
+    HTRI_HIP(hipMemcpyAsync(sc.p, scale, sizeof(double) * 21, hipMemcpyHostToDevice, s));
+    SampleArgs a = base_args(g, lut.p);
+    const int grid = (int)std::min<int64_t>(sample_grid(), (g.nw + kWavesPerBlock - 1) / kWavesPerBlock);
+    hipLaunchKernelGGL(k_wedge_importance, dim3(std::max(grid, 1)), dim3(kBlock), 0, s, a, sc.p, live, dev_out);
+    HTRI_LAUNCH_CHECK();
     HTRI_HIP(hipStreamSynchronize(s));
 }
 

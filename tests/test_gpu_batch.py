@@ -58,6 +58,62 @@ def test_graph_replays_agree_with_eager(htri, small_batch):
         assert y >= 0
 
 
+def test_full_pipeline_replay_matches_oracle(htri, small_batch):
+    """Step 1, work items and closure of every graph captured in one HIP
+    graph: every replay (with eager work and synchronisations in between)
+    gives the oracle's counts, as does the graph-by-graph baseline, and the
+    batch's other plans still count correctly afterwards."""
+    import torch
+    B = htri.Batch(small_batch)
+    want = np.array([core.OracleGraph(g.offsets, g.members, g.num_vertices).count(per_edge=False).H
+                     for g in small_batch])
+    x = torch.arange(1 << 16, device="cuda", dtype=torch.float32)
+    for sched in ((512, 256, 1), (256, 128, 0)):
+        for r in range(4):
+            got, ms = B.count_full(sched)
+            assert np.array_equal(got, want), (sched, r)
+            assert ms > 0
+            y = (x * r).sum().item()
+            torch.cuda.synchronize()
+            assert y >= 0
+        per, wall = B.count_full_per_graph(sched)
+        assert np.array_equal(per, want), sched
+        got, _ = B.count_full(sched)                  # replay after the graphs were rebuilt eagerly
+        assert np.array_equal(got, want), sched
+    got, _ = B.count_patterns((512, 256, 0), use_graph=True)
+    assert np.array_equal(got, want)
+    assert np.array_equal(B.wedges(), [G.build_wedges()[0] for G in
+                                       (htri.graph_load(g.offsets, g.members, g.num_vertices) for g in small_batch)])
+
+
+def test_size_class_schedules_and_their_cache(htri, small_batch, tmp_path):
+    """Per-size-class autotuning: the classes follow the hyperwedge counts,
+    the tuned schedules go to a JSON cache that a second call reads back
+    without timing, and counting with one schedule per class (eager or
+    graph-replayed) gives the oracle's counts."""
+    import json
+    B = htri.Batch(small_batch)
+    nw = B.wedges()
+    cls = B.size_classes()
+    assert np.array_equal(cls, np.where(nw < 2 ** 18, 0, np.where(nw < 2 ** 21, 1, 2)))
+    path = str(tmp_path / "schedules.json")
+    sc, ms, hit = B.autotune_classes(repeats=1, cache_path=path)
+    assert not hit
+    doc = json.load(open(path))
+    assert doc["format"] == "htri-batch-schedules" and len(doc["classes"]) == 3
+    for c in range(3):
+        assert (doc["classes"][c]["chunk"], doc["classes"][c]["partners"], doc["classes"][c]["order"]) == sc[c]
+        if (cls == c).any():
+            assert ms[c] > 0
+    sc2, _, hit2 = B.autotune_classes(repeats=1, cache_path=path)
+    assert hit2 and sc2 == sc
+    want = np.array([core.OracleGraph(g.offsets, g.members, g.num_vertices).count(per_edge=False).H
+                     for g in small_batch])
+    for use_graph in (False, True, True):
+        got, _ = B.count_classes(sc, use_graph=use_graph)
+        assert np.array_equal(got, want), use_graph
+
+
 def test_autotune_picks_a_valid_schedule(htri, small_batch):
     B = htri.Batch(small_batch[:8])
     sched, ms = B.autotune(repeats=1)
@@ -94,3 +150,15 @@ def test_full_batch_of_512_graphs(htri):
         assert rec is not None, f"no stored oracle count for graph {q}"
         assert got[q].tolist() == rec["H"], q
         assert nw[q] == rec["summary"][0], q
+    # step 1 + items + closure of all 512 graphs in one captured replay
+    full, ms = B.count_full(sched)
+    assert np.array_equal(full, got)
+    full2, ms2 = B.count_full(sched)
+    assert np.array_equal(full2, got)
+    print(f"[batch512] full pipeline replay {ms:.1f} / {ms2:.1f} ms", flush=True)
+    # one schedule per size class, tuned and replayed
+    print(f"[batch512] size classes {np.bincount(B.size_classes(), minlength=3).tolist()}", flush=True)
+    sc, cms, _ = B.autotune_classes(repeats=1)
+    bycls, cls_ms = B.count_classes(sc)
+    assert np.array_equal(bycls, got)
+    print(f"[batch512] class schedules {sc} ({cms}), replay {cls_ms:.1f} ms", flush=True)

@@ -300,3 +300,45 @@ def test_owner_with_many_incidences(htri):
     g = synth.from_lists(edges, 5001, "many-incidences")
     for flags in (htri.HTRI_DEDUPE_EDGES | htri.HTRI_ORDER_INPUT, htri.HTRI_DEDUPE_EDGES):
         check_exact(htri, g, flags=flags)
+
+
+@pytest.mark.parametrize("name", ["small0", "small5", "small9", "small11", "tiny", "clique", "coauth"])
+def test_class_targeted_ttt_counts(htri, name):
+    """Count-DenseTTT (patterns 9-16 by vertex groups and thick pairs; 9 alone
+    by its closed form), and Count-SparseTTT (patterns 17-20, the closure with
+    every hit holding a common vertex dropped), against the oracle's full
+    count, with the per-hyperedge counts of the sparse patterns."""
+    if name.startswith("small"):
+        q = int(name[5:])
+        g = synth.random_small(q, 50 + 5 * q, 5 + 3 * q, 1, 6)
+    elif name == "clique":
+        rng = np.random.default_rng(9)
+        edges = [[0] + sorted(rng.choice(np.arange(1, 200), size=2, replace=False).tolist()) for _ in range(900)]
+        edges += [[0, 1, 2] + sorted(rng.choice(np.arange(3, 90), size=3, replace=False).tolist()) for _ in range(300)]
+        edges.append(list(range(50, 250)))
+        g = synth.from_lists(edges, 260, "clique")
+    elif name == "coauth":
+        g = synth.generate(synth.config("coauth"))
+    else:
+        g = synth.generate(synth.config("tiny"))
+    G = htri.graph_load(g.offsets, g.members, g.num_vertices)
+    G.build_wedges()
+    o = core.OracleGraph(g.offsets, g.members, g.num_vertices)
+    r = o.count(edge_mask=0x1E0000)
+    H = r.H
+    cd, _, _ = G.count_patterns(window="dense_ttt")
+    assert np.array_equal(cd[9:17], H[9:17]), (cd, H)
+    assert (cd[1:9] == 0).all() and (cd[17:] == 0).all() and cd[0] == cd[1:].sum()
+    dense_ms = G.last_timings()[2]
+    cv, _, _ = G.count_patterns(window="common_vertex")
+    assert cv[9] == H[9] and cv[0] == H[9]
+    cs, pes, _ = G.count_patterns(window="sparse_ttt", per_edge=True, mask=0x1E0000)
+    assert np.array_equal(cs[17:21], H[17:21]) and (cs[1:17] == 0).all(), (cs, H)
+    assert np.array_equal(pes, r.t)
+    sparse_ms = G.last_timings()[2]
+    G.count_patterns()
+    full_ms = G.last_timings()[2]
+    print(f"\n[ttt] {name}: dense {dense_ms:.2f} ms, sparse {sparse_ms:.2f} ms, full closure {full_ms:.2f} ms; "
+          f"H9 {H[9]}", flush=True)
+    with pytest.raises(htri.HtriError):
+        G.count_patterns(window="dense_ttt", per_edge=True)

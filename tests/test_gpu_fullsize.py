@@ -50,6 +50,21 @@ def test_counts_equal_the_oracle_full_count(full):
     print(f"\n[fullsize] H and t equal the oracle's full count ({rec['H'][0]} triangles)", flush=True)
 
 
+def test_class_targeted_ttt_counts_at_full_size(full):
+    """Count-DenseTTT and Count-SparseTTT on the 5M-hyperedge graph equal the
+    oracle's per-pattern counts (stored full count)."""
+    rec = expected_counts(full["g"].sha256())
+    assert rec is not None, "no stored oracle count for this input"
+    G = full["G"]
+    cd, _, _ = G.count_patterns(window="dense_ttt")
+    dense_ms = G.last_timings()[2]
+    cs, _, _ = G.count_patterns(window="sparse_ttt")
+    sparse_ms = G.last_timings()[2]
+    assert cd[9:17].tolist() == rec["H"][9:17]
+    assert cs[17:21].tolist() == rec["H"][17:21]
+    print(f"\n[fullsize] DenseTTT {dense_ms:.1f} ms, SparseTTT {sparse_ms:.1f} ms", flush=True)
+
+
 def test_estimator_graph_counts_equal_the_oracle():
     """The samplers' evaluation graph (tags shape, seed 5): its exact count,
     which judges every estimate, equals the oracle's full count."""

@@ -340,3 +340,23 @@ def test_model_save_load_round_trip(htri, tmp_path):
     with pytest.raises(htri.HtriError):
         m2.load(bad)
     assert np.array_equal(m2.get_params(), m.get_params())
+
+
+@pytest.mark.parametrize("with_total", [False, True])
+def test_training_target_matches_oracle_closures(htri, with_total):
+    """htri_wedge_importance: log1p(sqrt(sum_p (c_p(w) |W| / H_p)^2) / n) of
+    every hyperwedge (with the total as a further term when asked), against
+    the same quantity from the oracle's per-wedge closures, in float64."""
+    g = synth.random_small(6, 400, 40, 1, 7)
+    G, o, rank = _setup(htri, g)
+    wi, wj, _ = o.wedges()
+    lo, hi = sampling.prec_wedge_order(rank, wi, wj)
+    C = o.wedge_closure_ranked(rank, lo, hi).astype(np.float64)
+    H = o.count(per_edge=False).H
+    nw = lo.shape[0]
+    live = np.concatenate([[with_total and H[0] > 0], H[1:] > 0])
+    scale = np.where(live, nw / np.where(H > 0, H, 1), 0.0)
+    want = np.log1p(np.sqrt(((C * scale) ** 2).sum(axis=1)) / max(live.sum(), 1))
+    got = G.wedge_importance(H, with_total=with_total).cpu().numpy()
+    assert got.shape == want.shape
+    assert np.allclose(got, want, rtol=2e-6, atol=1e-6)
