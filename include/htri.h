@@ -223,6 +223,27 @@ htri_status htri_count_patterns(htri_graph *g, uint32_t per_edge_pattern_mask, i
 htri_status htri_clustering_coefficient(const int64_t counts[21], int64_t connected_triples,
                                         const double epsilon[21], double *cc);
 
+/* Per-hyperedge counts of every pattern in one call (the hyperedge-level
+ * counts of the fine-grained clustering coefficient, Def. 5.1):
+ * per_edge_patterns int64[m][21] (normalised ids; [x][0] all patterns,
+ * [x][p] the hyper-triangles of pattern p holding x; host, or device with
+ * HTRI_OUTPUT_ON_DEVICE), counts int64[21] as htri_count_patterns.  Built
+ * from the full count's per-hyperedge counts, the search around the
+ * inclusion hyperwedges (patterns 1-8), the thick-pair scan of
+ * Count-DenseTTT (10-16) and one SparseTTT closure per present pattern of
+ * 17-20; pattern 9 is the remainder.  Errors: HTRI_E_INVALID, HTRI_E_STATE,
+ * HTRI_E_OOM, HTRI_E_DEVICE. */
+htri_status htri_count_per_edge_patterns(htri_graph *g, int64_t counts[21], int64_t *per_edge_patterns,
+                                         uint32_t out_flags);
+
+/* Local clustering coefficient of every hyperedge (normalised ids, double[m],
+ * host or device with HTRI_OUTPUT_ON_DEVICE): cc_x = sum_p epsilon[p]
+ * t[x][p] / C(deg_x, 2), deg_x = |N_{e_x}|, 0 when deg_x < 2; epsilon NULL
+ * weighs every pattern 1 (then cc_x = t_x / C(deg_x, 2), in [0, 1]), else
+ * each epsilon[p] in [0, 1] (Def. 5.1's weights applied per hyperedge).
+ * Errors: HTRI_E_INVALID, HTRI_E_STATE, HTRI_E_OOM, HTRI_E_DEVICE. */
+htri_status htri_local_clustering(htri_graph *g, const double epsilon[21], double *cc, uint32_t out_flags);
+
 /* List the hyper-triangles of one pattern (the enumeration half of the
  * problem statement, Section 2): pattern 1..20; out receives up to capacity
  * triples of normalised hyperedge ids, each sorted ascending, in no fixed

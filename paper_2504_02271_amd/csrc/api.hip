@@ -382,6 +382,56 @@ htri_status htri_count_patterns(htri_graph *h, uint32_t per_edge_pattern_mask, i
     });
 }
 
+htri_status htri_count_per_edge_patterns(htri_graph *h, int64_t counts[21], int64_t *per_edge_patterns,
+                                         uint32_t out_flags) {
+    if (!h || !counts || !per_edge_patterns || (out_flags & ~HTRI_OUTPUT_ON_DEVICE)) return HTRI_E_INVALID;
+    if (!h->g.have_wedges) {
+        h->g.err = "htri_build_wedges has not run";
+        return HTRI_E_STATE;
+    }
+    return run(&h->g, [&] {
+        htri::Graph &g = h->g;
+        const bool dev = out_flags & HTRI_OUTPUT_ON_DEVICE;
+        htri::DBuf<int64_t> tmp;
+        int64_t *out = per_edge_patterns;
+        if (!dev) {
+            tmp.alloc(g.al, std::max<int64_t>(g.m * 21, 1));
+            out = tmp.p;
+        }
+        int64_t c[21];
+        htri::count_per_edge_patterns(g, c, out);
+        if (!dev && g.m)
+            HTRI_HIP(hipMemcpyAsync(per_edge_patterns, out, sizeof(int64_t) * g.m * 21, hipMemcpyDeviceToHost, g.stream));
+        HTRI_HIP(hipStreamSynchronize(g.stream));
+        std::memcpy(counts, c, sizeof(c));
+    });
+}
+
+htri_status htri_local_clustering(htri_graph *h, const double epsilon[21], double *cc, uint32_t out_flags) {
+    if (!h || !cc || (out_flags & ~HTRI_OUTPUT_ON_DEVICE)) return HTRI_E_INVALID;
+    if (epsilon)
+        for (int p = 1; p <= 20; p++)
+            if (!(epsilon[p] >= 0.0 && epsilon[p] <= 1.0)) return HTRI_E_INVALID;
+    if (!h->g.have_wedges) {
+        h->g.err = "htri_build_wedges has not run";
+        return HTRI_E_STATE;
+    }
+    return run(&h->g, [&] {
+        htri::Graph &g = h->g;
+        if (g.m == 0) return;
+        const bool dev = out_flags & HTRI_OUTPUT_ON_DEVICE;
+        htri::DBuf<double> tmp;
+        double *out = cc;
+        if (!dev) {
+            tmp.alloc(g.al, g.m);
+            out = tmp.p;
+        }
+        htri::local_clustering(g, epsilon, out);
+        if (!dev) HTRI_HIP(hipMemcpyAsync(cc, out, sizeof(double) * g.m, hipMemcpyDeviceToHost, g.stream));
+        HTRI_HIP(hipStreamSynchronize(g.stream));
+    });
+}
+
 htri_status htri_last_timings(const htri_graph *h, double ms[6]) {
     if (!h || !ms) return HTRI_E_INVALID;
     ms[0] = h->g.tm.wedges_ms;

@@ -2044,7 +2044,8 @@ __global__ __launch_bounds__(kBlock) void k_incl_count(const int2 *pairs, const 
                                                        const int32_t *vadj, const uint8_t *lut_g, uint32_t emask,
                                                        unsigned long long *counts, unsigned long long *t,
                                                        int target, const int32_t *norm_of_rank, int64_t capacity,
-                                                       int32_t *out, unsigned long long *found) {
+                                                       int32_t *out, unsigned long long *found,
+                                                       unsigned long long *tp) {
     __shared__ unsigned long long cnt[21];
     __shared__ uint8_t lut[128];
     const int tid = threadIdx.x;
@@ -2089,6 +2090,11 @@ __global__ __launch_bounds__(kBlock) void k_incl_count(const int2 *pairs, const 
                 atomicAdd(&t[Lv], 1ull);
                 atomicAdd(&t[k], 1ull);
             }
+            if (tp) {   // per hyperedge and pattern (rank order, 21 per hyperedge)
+                atomicAdd(&tp[(int64_t)sv * 21 + p], 1ull);
+                atomicAdd(&tp[(int64_t)Lv * 21 + p], 1ull);
+                atomicAdd(&tp[(int64_t)k * 21 + p], 1ull);
+            }
         }
     }
     __syncthreads();
@@ -2116,7 +2122,8 @@ int64_t list_inclusion_wedges(Graph &g, DBuf<int64_t> &out) {
 }
 
 void count_inclusion_classes(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev, int target,
-                             int64_t capacity, int32_t *dev_out, unsigned long long *dev_found) {
+                             int64_t capacity, int32_t *dev_out, unsigned long long *dev_found,
+                             unsigned long long *tp_rank) {
     hipStream_t s = g.stream;
     Allocator &A = g.al;
     const int64_t m = g.m;
@@ -2149,7 +2156,7 @@ void count_inclusion_classes(Graph &g, uint32_t mask, int64_t counts[21], uint64
     if (nc > 0) {
         hipLaunchKernelGGL(k_incl_count, dim3((unsigned)nc), dim3(kBlock), 0, s, pairs.p, g.eptr.p, g.emem.p,
                            g.esize.p, g.vptr.p, g.vadj.p, lut.p, mask, ctr.p + 1, t_dev ? t.p : nullptr, target,
-                           g.norm_of_rank.p, capacity, dev_out, dev_found);
+                           g.norm_of_rank.p, capacity, dev_out, dev_found, tp_rank);
         HTRI_LAUNCH_CHECK();
     }
     HTRI_HIP(hipEventRecord(e2, s));

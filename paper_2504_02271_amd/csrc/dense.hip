@@ -317,7 +317,7 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_rest(const uint64_t *key,
                                                             int rbits, const int64_t *vptr, const int32_t *vadj,
                                                             const int64_t *eptr, const int32_t *emem,
                                                             const int32_t *esize, const uint8_t *glut,
-                                                            unsigned long long *part) {
+                                                            unsigned long long *part, unsigned long long *tp) {
     __shared__ uint2 tab[kDenseWaves][kHashSlots];   // (vertex + 1, bit 0: in x, bit 1: in y)
     __shared__ uint8_t lut[128];
     __shared__ unsigned long long red[kDenseBlock];
@@ -400,7 +400,14 @@ __global__ __launch_bounds__(kDenseBlock) void k_dense_rest(const uint64_t *key,
             if (gmin != v) continue;                                  // not the smallest common vertex
             if ((wxc >= 2 && c < y) || (wyc >= 2 && c < x)) continue; // an earlier thick pair counts it
             const int p = lut[region_bits(sx, sy, esize[c], wxy, wxc, wyc, g)];
-            if (p >= 10 && p <= 16) cnt[p - 10]++;
+            if (p >= 10 && p <= 16) {
+                cnt[p - 10]++;
+                if (tp) {   // per hyperedge and pattern (rank order, 21 per hyperedge)
+                    atomicAdd(&tp[(int64_t)x * 21 + p], 1ull);
+                    atomicAdd(&tp[(int64_t)y * 21 + p], 1ull);
+                    atomicAdd(&tp[(int64_t)c * 21 + p], 1ull);
+                }
+            }
         }
     }
     for (int p = 0; p < 7; p++) block_sum_u64(cnt[p], red, part + (int64_t)p * gridDim.x);
@@ -424,7 +431,7 @@ unsigned long long sum_parts(const unsigned long long *dev, int n, hipStream_t s
 
 // DenseTTT counts: counts[9..16] (others 0).  rest: also patterns 10-16
 // (false: pattern 9 alone).  ms: device time.
-void count_dense_ttt(Graph &g, bool rest, int64_t counts[21], float *ms) {
+void count_dense_ttt(Graph &g, bool rest, int64_t counts[21], float *ms, unsigned long long *tp_rank) {
     hipStream_t s = g.stream;
     Allocator &A = g.al;
     for (int p = 0; p < 21; p++) counts[p] = 0;
@@ -492,7 +499,7 @@ void count_dense_ttt(Graph &g, bool rest, int64_t counts[21], float *ms) {
                                                   (int64_t)device_cu_count() * 16);
             DBuf<unsigned long long> pr(A, (size_t)gw * 7);
             hipLaunchKernelGGL(k_dense_rest, dim3(gw), dim3(kDenseBlock), 0, s, key.p, val.p, nrec, rbits, g.vptr.p,
-                               g.vadj.p, g.eptr.p, g.emem.p, g.esize.p, lut.p, pr.p);
+                               g.vadj.p, g.eptr.p, g.emem.p, g.esize.p, lut.p, pr.p, tp_rank);
             HTRI_LAUNCH_CHECK();
             std::vector<unsigned long long> h((size_t)gw * 7);
             HTRI_HIP(hipMemcpyAsync(h.data(), pr.p, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost, s));

@@ -400,7 +400,8 @@ bool valid_config(const CloseConfig &cfg);
 // dev_out, also the triangles of pattern target (sorted normalised triples)
 void count_inclusion_classes(Graph &g, uint32_t mask, int64_t counts[21], uint64_t *t_dev /*m or null*/,
                              int target = 0, int64_t capacity = 0, int32_t *dev_out = nullptr,
-                             unsigned long long *dev_found = nullptr);
+                             unsigned long long *dev_found = nullptr,
+                             unsigned long long *tp_rank = nullptr /* m*21, rank order, accumulated */);
 // every hyperwedge closed, the triangles of pattern target listed
 void enumerate_all_wedges(Graph &g, int target, int64_t capacity, int32_t *dev_out, unsigned long long *dev_found);
 void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21], uint64_t *t_dev /*m or null*/,
@@ -423,8 +424,15 @@ void sample_sums(Graph &g, int mode, int64_t n, uint64_t seed, const int64_t *po
 int64_t list_inclusion_wedges(Graph &g, DBuf<int64_t> &out);
 // sample.hip: the learned proposal's training target of every hyperwedge
 void wedge_importance_all(Graph &g, const double scale[21], double live, float *dev_out);
-// dense.hip: DenseTTT counts (patterns 9-16, or 9 alone) into counts[21]
-void count_dense_ttt(Graph &g, bool rest, int64_t counts[21], float *ms);
+// dense.hip: DenseTTT counts (patterns 9-16, or 9 alone) into counts[21];
+// tp_rank (m*21, rank order, accumulated): per-hyperedge counts of 10-16
+void count_dense_ttt(Graph &g, bool rest, int64_t counts[21], float *ms,
+                     unsigned long long *tp_rank = nullptr);
+// perpattern.hip: per-hyperedge counts of every pattern (normalised ids,
+// m*21 int64 on the device, [x][0] = all patterns) and the counts
+void count_per_edge_patterns(Graph &g, int64_t counts[21], int64_t *dev_out);
+// local clustering coefficients (normalised ids, device double[m])
+void local_clustering(Graph &g, const double eps[21], double *dev_cc);
 // advanced.hip: Appro-adv's draw split (alpha1..alpha4) and its estimate
 void adv_split(int64_t n_inter, int64_t n_incl, int64_t alpha, int64_t out[4]);
 void adv_estimate(Graph &g, int64_t alpha, uint64_t seed, double est[21], double se[21], int64_t alphas[4]);

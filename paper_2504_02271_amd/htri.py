@@ -107,6 +107,8 @@ def load_library() -> ctypes.CDLL:
         "htri_enumerate": ([_P, _i32, _i64, _P, _P, _u32], ctypes.c_int),
         "htri_clustering_coefficient": ([_P, _i64, _P, _P], ctypes.c_int),
         "htri_get_wedge_list": ([_P, _P, _i64, _P, _P, _P], ctypes.c_int),
+        "htri_count_per_edge_patterns": ([_P, _P, _P, _u32], ctypes.c_int),
+        "htri_local_clustering": ([_P, _P, _P, _u32], ctypes.c_int),
         "htri_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "htri_last_error": ([_P], ctypes.c_char_p),
         "htri_graph_free": ([_P], None),
@@ -326,6 +328,23 @@ class Graph:
         _check(self._lib.htri_count_patterns(self._h, mask, _ptr(counts), pe_p, pw_p, flags),
                "htri_count_patterns", self._h)
         return counts, pe, pw
+
+    def count_per_edge_patterns(self):
+        """(counts int64[21], per-hyperedge per-pattern counts int64[m, 21])."""
+        counts = np.zeros(21, np.int64)
+        out = np.zeros((max(self.num_edges, 1), 21), np.int64)
+        _check(self._lib.htri_count_per_edge_patterns(self._h, _ptr(counts), _ptr(out), 0),
+               "htri_count_per_edge_patterns", self._h)
+        return counts, out[: self.num_edges]
+
+    def local_clustering(self, epsilon=None) -> np.ndarray:
+        """Local clustering coefficient of every hyperedge (float64[m])."""
+        e = None if epsilon is None else np.ascontiguousarray(epsilon, dtype=np.float64)
+        if e is not None and e.shape != (21,):
+            raise ValueError("epsilon holds 21 weights (index 0 unused)")
+        out = np.zeros(max(self.num_edges, 1), np.float64)
+        _check(self._lib.htri_local_clustering(self._h, _ptr(e), _ptr(out), 0), "htri_local_clustering", self._h)
+        return out[: self.num_edges]
 
     def enumerate(self, pattern: int, capacity: int = 1 << 20):
         """(triples int32 [min(found, capacity), 3] of normalised ids, found)."""

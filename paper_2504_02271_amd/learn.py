@@ -107,7 +107,7 @@ def pool_factor_for(n: int, nw: int, pool_factor: float = POOL_FACTOR,
 
 def equal_time_study(G, exact: np.ndarray, model, budgets: Sequence[float] = (0.001, 0.01, 0.05),
                      seeds: int = 32, mix: float = 0.1, pool_factor="auto",
-                     log=print, exact_inclusion: bool = False) -> List[Dict]:
+                     log=print, exact_inclusion: bool = False, with_adv: bool = True) -> List[Dict]:
     """Learned vs uniform hyperwedge sampling at equal GPU time.  For each
     budget b: the learned sampler draws b*|wedges| samples (from a uniform pool
     of pool_factor times as many candidates, or from all wedges with pool
@@ -115,7 +115,8 @@ def equal_time_study(G, exact: np.ndarray, model, budgets: Sequence[float] = (0.
     time budget; the uniform sampler gets as many samples as fit in that time
     (calibrated to within 5%).  Errors over `seeds` independent runs.
     exact_inclusion: both samplers close the inclusion stratum exactly and
-    sample the intersection-type hyperwedges."""
+    sample the intersection-type hyperwedges.  with_adv: also Appro-adv
+    (Algorithm 7) at the same time (plain study only)."""
     xi = exact_inclusion
     nw = G.num_wedges
     out = []
@@ -148,7 +149,7 @@ def equal_time_study(G, exact: np.ndarray, model, budgets: Sequence[float] = (0.
                "learned_rel_err": float(np.mean(rl)), "uniform_rel_err": float(np.mean(ru))}
         row.update(_error_summary("learned", np.array(el), exact))
         row.update(_error_summary("uniform", np.array(eu), exact))
-        if not xi:
+        if with_adv and not xi:
             # Appro-adv (Algorithm 7) at the same time: its draw count calibrated like uniform's
             nA = nL
             for _ in range(6):
@@ -171,7 +172,8 @@ def equal_time_study(G, exact: np.ndarray, model, budgets: Sequence[float] = (0.
         log(f"[equal-time] budget {b:g}: learned n={nL} {t_target:.2f} ms err {row['learned_rel_err']:.4f} "
             f"(total {row['learned_total_rel_err']:.2e}) | uniform n={nU} {row['uniform_ms']:.2f} ms err "
             f"{row['uniform_rel_err']:.4f} (total {row['uniform_total_rel_err']:.2e})"
-            + (f" | adv n={row['adv_samples']} {row['adv_ms']:.2f} ms err {row['adv_rel_err']:.4f}" if not xi else ""))
+            + (f" | adv n={row['adv_samples']} {row['adv_ms']:.2f} ms err {row['adv_rel_err']:.4f}"
+               if "adv_samples" in row else ""))
         out.append(row)
     return out
 

@@ -154,7 +154,13 @@ def test_invalid_arguments(htri):
         G.enumerate(21)
     assert e.value.code == -1
     with pytest.raises(htri.HtriError) as e:
-        G.estimate(num_samples=10, proposal=2)
+        G.estimate(num_samples=10, proposal=3)
+    assert e.value.code == -1
+    with pytest.raises(htri.HtriError) as e:
+        G.estimate(num_samples=10, proposal=2, exact_inclusion=True)
+    assert e.value.code == -1
+    with pytest.raises(htri.HtriError) as e:
+        G.local_clustering(np.full(21, -0.5))
     assert e.value.code == -1
     # the handle still works after the refusals
     counts, _, _ = G.count_patterns()
