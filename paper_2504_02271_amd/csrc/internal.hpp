@@ -230,6 +230,7 @@ struct Graph {
     int64_t nnz = 0;        // memberships after removing repeated ids
     int32_t n = 0;          // vertices
     int32_t max_size = 0;
+    int32_t min_size = 0;       // smallest hyperedge size (0 for an empty graph)
 
     // normalised-id CSR (input order of survivors)
     DBuf<int64_t> eptr_n;

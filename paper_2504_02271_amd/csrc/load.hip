@@ -142,15 +142,31 @@ __global__ void k_vertex_degree(const int32_t *mem, int64_t nnz, int64_t *dv) {
 // delta_x = sum over v in e_x of (|E_v| - 1); sort key with x as payload
 __global__ void k_delta(const int64_t *eptr, const int32_t *emem, int64_t m, const int64_t *dv,
                         uint64_t *key, uint32_t *val, int32_t *size, unsigned int *maxsize) {
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < m;
-         x += (int64_t)gridDim.x * blockDim.x) {
-        uint64_t d = 0;
-        for (int64_t t = eptr[x]; t < eptr[x + 1]; t++) d += (uint64_t)(dv[emem[t]] - 1);
-        key[x] = d;
-        val[x] = (uint32_t)x;
-        int32_t s = (int32_t)(eptr[x + 1] - eptr[x]);
-        size[x] = s;
-        atomicMax(maxsize, (unsigned int)s);
+    // every lane of a wave runs the same iterations (the wave reductions
+    // below read all 64 lanes); lanes past m contribute the identities
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
+        const int64_t x = base + threadIdx.x;
+        unsigned int hi = 0u, lo = 0xFFFFFFFFu;
+        if (x < m) {
+            uint64_t d = 0;
+            for (int64_t t = eptr[x]; t < eptr[x + 1]; t++) d += (uint64_t)(dv[emem[t]] - 1);
+            key[x] = d;
+            val[x] = (uint32_t)x;
+            const int32_t s = (int32_t)(eptr[x + 1] - eptr[x]);
+            size[x] = s;
+            hi = lo = (unsigned int)s;
+        }
+        // largest and smallest size: one atomic of each per wave
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            hi = max(hi, (unsigned int)__shfl_xor((int)hi, o, 64));
+            lo = min(lo, (unsigned int)__shfl_xor((int)lo, o, 64));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            if (hi) atomicMax(&maxsize[0], hi);
+            if (lo != 0xFFFFFFFFu) atomicMin(&maxsize[1], lo);
+        }
     }
 }
 
@@ -374,8 +390,9 @@ void graph_load(Graph &g, const int64_t *off_in, int64_t m_in, const int32_t *me
         DBuf<uint64_t> key(A, m);
         DBuf<uint32_t> val(A, m);
         DBuf<int32_t> size_n(A, m);
-        DBuf<unsigned int> mx(A, 1);
+        DBuf<unsigned int> mx(A, 2);              // largest, smallest size
         fill_u32(mx.p, 1, 0, s);
+        fill_u32(mx.p + 1, 1, 0xFFFFFFFFu, s);
         if (m > 0) {
             hipLaunchKernelGGL(k_delta, dim3(grid_for(m, 256)), dim3(256), 0, s, g.eptr_n.p, g.emem_n.p, m,
                                dv.p, key.p, val.p, size_n.p, mx.p);
@@ -386,6 +403,7 @@ void graph_load(Graph &g, const int64_t *off_in, int64_t m_in, const int32_t *me
             radix_sort_u64(A, key.p, val.p, m, bits_for((uint64_t)g.nnz), s);
         }
         g.max_size = (int32_t)read_scalar(mx.p, s);
+        g.min_size = m > 0 ? (int32_t)read_scalar(mx.p + 1, s) : 0;
         if (m > 0) {
             hipLaunchKernelGGL(k_rank_maps, dim3(grid_for(m, 256)), dim3(256), 0, s, val.p, m,
                                g.norm_of_rank.p, g.rank_of_norm.p, size_n.p, g.esize.p, esize64.p);
