@@ -550,7 +550,8 @@ def main() -> int:
         "ttt_subclasses": {
             "what": "Count-DenseTTT (patterns 9-16: pattern 9 per vertex by inclusion-exclusion over the "
                     "thick pairs, 10-16 from the thick hyperwedges) and Count-SparseTTT (17-20: the closure "
-                    "with every hit holding a common vertex dropped, no dense window); device ms, median of 3; "
+                    "with every hit holding a common vertex dropped, in the window and the probing alike; the "
+                    "window's bulk common-vertex counting skipped); device ms, median of 3; "
                     "both equal to the full count's",
             "dense_ttt_ms": float(np.median(dense_ms)),
             "sparse_ttt_ms": float(np.median(sparse_ms)),

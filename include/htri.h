@@ -189,7 +189,9 @@ htri_status htri_get_wedge_list(const htri_graph *g, const int64_t *wedge_idx, i
  *               outside the class are 0.  SPARSE_TTT counts patterns 17-20
  *               (Count-SparseTTT: the closure with every hit that has a
  *               vertex common to all three hyperedges dropped as soon as
- *               g > 0 is known, no dense window); per_edge counts the
+ *               g > 0 is known; the dense window, where chosen, enumerates
+ *               its hits the same way and skips its bulk counting of the
+ *               common-vertex pattern); per_edge counts the
  *               masked patterns among 17-20, per_wedge must be NULL.  The last counts only the
  *               classes whose hyper-triangles hold an inclusion hyperwedge
  *               (patterns 1-8; Count-CCC, Count-TCC and Count-TTC of

@@ -1737,6 +1737,9 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
             } else {
                 g = triple_common(G.eptr, G.emem, r, j, k);
             }
+            // SparseTTT-only counting (emask bit 31): a hit with a vertex
+            // common to all three hyperedges is dropped
+            if (((A.emask >> 31) & 1u) && g > 0) return false;
             const uint32_t p = A.lut[region_mask(si, sj, sk, wij, wik, wjk, g)];
             atomicAdd(&cnt[p], 1ull);
             enumerated++;
@@ -1851,7 +1854,7 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
                 fast += __shfl_xor(fast, o, kWave);
             }
             if (pl == 0 && qv) {
-                if (fast) atomicAdd(&cnt[kPatternCommonVertex], (unsigned long long)fast);
+                if (fast && !((A.emask >> 31) & 1u)) atomicAdd(&cnt[kPatternCommonVertex], (unsigned long long)fast);
                 if (PER_WEDGE) A.cwj[base + q] = all;
                 // the enumerated hits add theirs when they are classified
                 if (PER_EDGE && count9 && fast) atomicAdd(&A.cwjm[base + q], fast);
@@ -1875,7 +1878,7 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
 WindowPlan choose_window(Graph &g, uint32_t flags) {
     WindowPlan w;
     w.w0 = g.m;
-    if ((flags & (HTRI_COUNT_NO_WINDOW | HTRI_COUNT_SPARSE_TTT)) || g.m < 3 || g.nw == 0) return w;
+    if ((flags & HTRI_COUNT_NO_WINDOW) || g.m < 3 || g.nw == 0) return w;
     auto fptr_at = [&](int64_t i) {
         int64_t v = 0;
         HTRI_HIP(hipMemcpyAsync(&v, g.fptr.p + i, sizeof(int64_t), hipMemcpyDeviceToHost, g.stream));
@@ -2383,7 +2386,7 @@ void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21],
     a.probes = ctr.p + 22;
     a.staged = ctr.p + 28;
     a.tedge = mid && pe ? tsum.p : nullptr;
-    close_window(g, win, mask, lut.p, ctr.p + 1, ctr.p + 26, cw_dev, pe ? cwjm.p : nullptr, pe ? cwkm.p : nullptr);
+    close_window(g, win, a.emask, lut.p, ctr.p + 1, ctr.p + 26, cw_dev, pe ? cwjm.p : nullptr, pe ? cwkm.p : nullptr);
     HTRI_HIP(hipEventRecord(ew, s));
     launch_close_kernel(cfg, pe, pw, a, nblocks, s, mid);
     HTRI_HIP(hipEventRecord(e2, s));
