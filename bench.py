@@ -104,7 +104,6 @@ def estimator_study(seeds: int, log_fn):
     t0 = time.time()
     train = [synth.generate(sp) for sp in synth.training_specs(20)]
     X, y = learn.training_rows(train, rows_per_graph=200_000, top_rows=50_000, seed=0, target="importance")
-    del train
     model = learn.train_proposal(X, y, steps=3000, batch=4096, lr=2e-3, seed=0)
     torch.cuda.synchronize()
     train_s = time.time() - t0
@@ -122,13 +121,12 @@ def estimator_study(seeds: int, log_fn):
         r["learned_wins"] = r["learned_rel_err"] < r["uniform_rel_err"]
     rows_sigma = learn.sigma_study(G, exact, sigmas=(1.0, 0.5, 0.25), seeds=8, budget=0.01, log=log_fn)
     # the same network trained with the total count as one more term of its target
-    train = [synth.generate(sp) for sp in synth.training_specs(20)]
     Xt, yt = learn.training_rows(train, rows_per_graph=200_000, top_rows=50_000, seed=0, target="importance_total")
     del train
     model_t = learn.train_proposal(Xt, yt, steps=3000, batch=4096, lr=2e-3, seed=0)
     del Xt, yt
     log_fn("[bench] proposal with the total in its target ...")
-    rows_t = learn.equal_time_study(G, exact, model_t, budgets=(0.001, 0.01, 0.05), seeds=max(8, seeds // 2),
+    rows_t = learn.equal_time_study(G, exact, model_t, budgets=(0.001, 0.01, 0.05), seeds=max(8, seeds // 4),
                                     log=log_fn, with_adv=False)
     for r in rows_t:
         r["learned_wins"] = r["learned_rel_err"] < r["uniform_rel_err"]
@@ -150,7 +148,7 @@ def estimator_study(seeds: int, log_fn):
                            "two hyperwedge types, as in Appro-adv, with the inclusion stratum exhausted)",
         "budgets_total_target": rows_t,
         "total_target": "third study: the same network trained on log1p of the importance with the total "
-                        "count as one more term (HTRI_IMPORTANCE_TOTAL), plain sampling, half the seeds",
+                        "count as one more term (HTRI_IMPORTANCE_TOTAL), plain sampling, a quarter of the seeds",
         "sigma_sampling": {
             "what": "Appro-bs with sigma: a uniform subset of floor(sigma*m+1/2) hyperedges, 1% of the induced "
                     "subgraph's hyperwedges sampled uniformly, the estimate times m(m-1)(m-2)/(n(n-1)(n-2)); "

@@ -24,8 +24,10 @@
 // through a 128-entry region-emptiness table (the common-vertex pattern by a
 // shortcut test).  Persistent blocks pull items from two queues (block items,
 // then single-middle wave items).  Pattern counts live one per lane (lane p
-// holds pattern p) and are added to the global counts once per wave when
-// the wave moves to another graph or finishes; per-hyperedge counts come
+// holds pattern p); in a single-graph launch each wave (each window block)
+// writes them to its own slot when it finishes and a fixed-order reduction
+// sums the slots, in a batched launch a wave adds them to its graph's counts
+// when it moves to another graph or finishes.  Per-hyperedge counts come
 // from per-wedge role counters and per-wave sums added to the hyperedges'
 // totals during the closure.
 #include <algorithm>
@@ -1078,7 +1080,35 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
     }
     if (lane == 0 && wprobes) atomicAdd(A.probes, wprobes);
     if (lane == 0 && wstaged && A.staged) atomicAdd(A.staged, wstaged);
-    if (cur_g >= 0) flush_wave_counts(wcnt, c9, A.counts, cur_g, lane);
+    if (A.wave_part) {
+        // one graph: every wave writes its 21 counts to its own slot (zeros
+        // if it closed nothing); a fixed-order reduction adds them up
+        unsigned long long s9 = c9;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) s9 += __shfl_xor(s9, o, kWave);
+        if (lane == (int)kPatternCommonVertex) wcnt += s9;
+        const int64_t gw = (int64_t)blockIdx.x * (kBlock / kWave) + wave;
+        if (lane < 21) A.wave_part[gw * 21 + lane] = lane >= 1 ? wcnt : 0ull;
+    } else if (cur_g >= 0) {
+        flush_wave_counts(wcnt, c9, A.counts, cur_g, lane);
+    }
+}
+
+// counts[p] += sum_i part[i * 21 + p]: block p sums a strided share per
+// thread, then a tree in shared memory (fixed order, no atomics)
+__global__ __launch_bounds__(256) void k_sum_parts(const unsigned long long *part, int64_t n,
+                                                   unsigned long long *counts) {
+    __shared__ unsigned long long red[256];
+    const int p = blockIdx.x + 1;
+    unsigned long long v = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) v += part[i * 21 + p];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[p] += red[0];
 }
 
 // Work items per owner: block items in cnt, and wcnt = 1 for an owner closed
@@ -1235,6 +1265,12 @@ struct CloseVariants {
 };
 
 }  // namespace
+
+void sum_pattern_parts(const unsigned long long *part, int64_t n, unsigned long long *counts, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_sum_parts, dim3(20), dim3(256), 0, s, part, n, counts);
+    HTRI_LAUNCH_CHECK();
+}
 
 bool valid_config(const CloseConfig &c) {
     return (c.cap == 256 || c.cap == 512) && (c.jp == 128 || c.jp == 256);
@@ -1579,6 +1615,7 @@ struct WinArgs {
     uint32_t emask;
     unsigned int *queue;
     unsigned long long *counts;     // [21]
+    unsigned long long *block_part; // each block's pattern counts [blocks][21], summed afterwards
     unsigned long long *stats;      // [0] bitmap words read, [1] hits enumerated
     uint32_t *cwj, *cwjm, *cwkm;
 };
@@ -1863,7 +1900,7 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
         if (qn > 0) flush();
     }
     __syncthreads();
-    if (tid >= 1 && tid < 21 && cnt[tid]) atomicAdd(&A.counts[tid], cnt[tid]);
+    if (tid < 21) A.block_part[(int64_t)blockIdx.x * 21 + tid] = tid >= 1 ? cnt[tid] : 0ull;
     // words_read is per wave (lane 0's copy counts); enumerated is per lane
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) enumerated += __shfl_xor(enumerated, o, kWave);
@@ -1951,11 +1988,14 @@ void close_window(Graph &g, const WindowPlan &w, uint32_t emask, const uint8_t *
     else oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_close_window<false, false>, kBlock, shmem);
     if (oe != hipSuccess || nb < 1) nb = 1;
     const int grid = (int)std::min<int64_t>((int64_t)device_cu_count() * nb, w.nrows);
+    DBuf<unsigned long long> bpart(g.al, (int64_t)grid * 21);
+    a.block_part = bpart.p;
     if (pe && pw) hipLaunchKernelGGL((k_close_window<true, true>), dim3(grid), dim3(kBlock), shmem, s, a);
     else if (pe) hipLaunchKernelGGL((k_close_window<true, false>), dim3(grid), dim3(kBlock), shmem, s, a);
     else if (pw) hipLaunchKernelGGL((k_close_window<false, true>), dim3(grid), dim3(kBlock), shmem, s, a);
     else hipLaunchKernelGGL((k_close_window<false, false>), dim3(grid), dim3(kBlock), shmem, s, a);
     HTRI_LAUNCH_CHECK();
+    sum_pattern_parts(bpart.p, grid, counts, s);
     // the bitmaps are freed when this returns: wait for the kernels
     HTRI_HIP(hipStreamSynchronize(s));
 }
@@ -2386,10 +2426,13 @@ void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21],
     a.probes = ctr.p + 22;
     a.staged = ctr.p + 28;
     a.tedge = mid && pe ? tsum.p : nullptr;
+    DBuf<unsigned long long> wpart(A, (int64_t)nblocks * (kBlock / kWave) * 21);
+    a.wave_part = wpart.p;
     close_window(g, win, a.emask, lut.p, ctr.p + 1, ctr.p + 26, cw_dev, pe ? cwjm.p : nullptr, pe ? cwkm.p : nullptr);
     HTRI_HIP(hipEventRecord(ew, s));
     launch_close_kernel(cfg, pe, pw, a, nblocks, s, mid);
     HTRI_HIP(hipEventRecord(e2, s));
+    sum_pattern_parts(wpart.p, (int64_t)nblocks * (kBlock / kWave), a.counts, s);
 
     if (pe) {
         DBuf<unsigned long long> &t = tsum;

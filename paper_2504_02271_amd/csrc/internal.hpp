@@ -347,7 +347,13 @@ struct CloseArgs {
     unsigned long long *tedge;      // middle-centric with per-edge counts: per-hyperedge totals by
                                     // rank, to which each item adds its middle's j-role counts and
                                     // its hashed entries' k-role counts (cwkm is left to the window)
+    unsigned long long *wave_part = nullptr;   // single-graph launches: each wave's pattern counts,
+                                               // [waves][21], summed afterwards in a fixed order
+                                               // (null: each wave adds its counts per graph)
 };
+// counts[p] += sum over i of part[i][p], p = 1..20, in a fixed order (one
+// block per pattern, no atomics)
+void sum_pattern_parts(const unsigned long long *part, int64_t n, unsigned long long *counts, hipStream_t s);
 // Owners with at most kWaveOwnerMax forward entries whose partner lists hold
 // at most kWaveStreamMax entries in total are closed by one wave each.
 constexpr int kWaveOwnerMax = 64;
