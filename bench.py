@@ -311,6 +311,19 @@ def cpu_baseline(g, workload: str, log_fn):
     a = res["all_threads"]
     total_s = norm_s + step1_s + a["closure_whole_graph_s_scaled"] if a["closure_whole_graph_s_scaled"] else None
     o1 = res["one_thread"]
+    m_all = o.m
+    del o
+    # a whole count the host finishes in seconds: the co-authorship-shaped graph
+    from paper_2504_02271_amd import synth
+    gc = synth.generate(synth.config("coauth"))
+    t0 = time.perf_counter()
+    oc = core.OracleGraph(gc.offsets, gc.members, gc.num_vertices)
+    oc.build_wedges(nthreads=threads)
+    rc = oc.count(nthreads=threads, per_edge=True)
+    coauth_s = time.perf_counter() - t0
+    nwc = int(oc.summary()[0])
+    log_fn(f"[bench] oracle whole count of the co-authorship graph: {nwc} hyperwedges, {int(rc.H[0])} "
+           f"hyper-triangles in {coauth_s:.1f} s on {threads} threads")
     return {
         "value": nw / total_s if total_s else None,
         "unit": "hyperwedges/s",
@@ -320,7 +333,7 @@ def cpu_baseline(g, workload: str, log_fn):
         "cpu_model": _cpu_model(),
         "nproc": os.cpu_count(),
         "sample": (f"plain two-step oracle: normalise {norm_s:.2f} s (1 thread) and step 1 {step1_s:.2f} s "
-                   f"({threads} threads) over all {o.m} hyperedges; closure over 16 evenly spaced owner "
+                   f"({threads} threads) over all {m_all} hyperedges; closure over 16 evenly spaced owner "
                    f"ranges ({a['sample_owners']} owners, {a['sample_triangles']} hyper-triangles) in "
                    f"{a['sample_closure_s']} s on {threads} threads, scaled by the sample's share "
                    f"{a['triangle_share']} of the oracle's stored total {T_total}; value = {nw} hyperwedges / "
@@ -331,6 +344,9 @@ def cpu_baseline(g, workload: str, log_fn):
         "closure": res,
         "one_thread_closure_rate_triangles_per_s": o1["sample_triangles"] / o1["sample_closure_s"]
         if o1["sample_closure_s"] else None,
+        "whole_count_coauth": {"workload": "co-authorship-shaped, |E|=5e5, seed 2", "hyperedges": int(oc.m),
+                               "hyperwedges": nwc, "triangles": int(rc.H[0]), "threads": threads,
+                               "seconds": round(coauth_s, 3), "hyperwedges_per_s": nwc / coauth_s},
     }
 
 
