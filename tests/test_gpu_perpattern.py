@@ -127,6 +127,13 @@ def test_local_clustering(htri, name):
 
 
 def test_per_edge_patterns_empty_and_wedgeless(htri):
+    g = synth.from_lists([], 5, "empty")
+    G = htri.graph_load(g.offsets, g.members, 5)
+    G.build_wedges()
+    counts, t = G.count_per_edge_patterns()
+    assert not counts.any() and t.shape == (0, 21)
+    assert G.local_clustering().shape == (0,)
+    G.close()
     g = synth.from_lists([[0, 1], [2, 3], [4, 5, 6]], 7, "wedgeless")
     G = htri.graph_load(g.offsets, g.members, g.num_vertices)
     G.build_wedges()
