@@ -523,7 +523,7 @@ def main() -> int:
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_close (probing closure + classify + per-block reduce, owners outside the dense window; "
+            "kernel": "k_close (probing closure + classify + per-wave pattern counts, owners outside the dense window; "
                       + ("middle-centric" if int(cstats[12]) == 1 else "owner-centric") + " probing)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
