@@ -23,8 +23,10 @@
  *               at its two smallest ids -- the hyperwedge order O of Section 2
  *               and the i<min{j,k} rule of Algorithm 1.
  *   classify    the seven regions a..g of Section 2 (Def. 2.4 and the text
- *               after it), with g = |e_i & e_j & e_k| taken by a three-way
- *               merge of the sorted member lists; classes with inclusion
+ *               after it), with g = |e_i & e_j & e_k| taken as |Omega_ij & e_k|
+ *               (Omega_ij, the common vertices of the hyperwedge (Def. 2.2),
+ *               listed once per hyperwedge by merging the two sorted member
+ *               lists, then merged with e_k); classes with inclusion
  *               hyperwedges follow the rules of Algorithm 5 (Count-CCC,
  *               Count-TCC, Count-TTC), the intersection-only class (TTT) is
  *               numbered from which regions are empty.
