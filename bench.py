@@ -455,6 +455,16 @@ def main() -> int:
     log(f"[bench] DenseTTT (patterns 9-16) {np.median(dense_ms):.2f} ms, SparseTTT (17-20) "
         f"{np.median(sparse_ms):.2f} ms, full closure {close_ms:.2f} ms")
 
+    # per-hyperedge counts of all 20 patterns in one call (wall time, output kept on the device)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    cpp, tpp = G.count_per_edge_patterns(device_out=True)
+    torch.cuda.synchronize()
+    pp_ms = (time.time() - t0) * 1e3
+    assert np.array_equal(cpp, counts), "per-hyperedge per-pattern call gives other pattern counts"
+    del tpp
+    log(f"[bench] per-hyperedge counts of every pattern: {pp_ms:.1f} ms")
+
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle ...")
@@ -570,6 +580,12 @@ def main() -> int:
             "dense_ttt_ms": float(np.median(dense_ms)),
             "sparse_ttt_ms": float(np.median(sparse_ms)),
             "full_closure_ms": close_ms,
+        },
+        "per_edge_patterns": {
+            "what": "htri_count_per_edge_patterns: int64[m][21] per-hyperedge counts of every pattern (full count, "
+                    "patterns 1-8 around the inclusion hyperwedges, Count-DenseTTT, one SparseTTT closure, "
+                    "pattern 9 as the remainder), output on the device; wall ms of one call",
+            "ms": pp_ms,
         },
         "cpu_baseline": cpu,
         "estimator": study,

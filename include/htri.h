@@ -232,8 +232,9 @@ htri_status htri_clustering_coefficient(const int64_t counts[21], int64_t connec
  * HTRI_OUTPUT_ON_DEVICE), counts int64[21] as htri_count_patterns.  Built
  * from the full count's per-hyperedge counts, the search around the
  * inclusion hyperwedges (patterns 1-8), the thick-pair scan of
- * Count-DenseTTT (10-16) and one SparseTTT closure per present pattern of
- * 17-20; pattern 9 is the remainder.  Errors: HTRI_E_INVALID, HTRI_E_STATE,
+ * Count-DenseTTT (10-16) and one SparseTTT closure (17-20), each adding
+ * a hyper-triangle to its three hyperedges' counts of its pattern; pattern 9
+ * is the remainder.  Errors: HTRI_E_INVALID, HTRI_E_STATE,
  * HTRI_E_OOM, HTRI_E_DEVICE. */
 htri_status htri_count_per_edge_patterns(htri_graph *g, int64_t counts[21], int64_t *per_edge_patterns,
                                          uint32_t out_flags);

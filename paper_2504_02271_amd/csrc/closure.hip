@@ -225,7 +225,7 @@ struct JParams {
 // other hits.  hit[u]: entry u closes a hyper-triangle; mhit[u]: it counts
 // towards the per-hyperedge counts; po[u]: its pattern unless it is the
 // common-vertex one (counted in c9), else 0.
-template <int U, bool PER_EDGE, typename JF>
+template <int U, bool PER_EDGE, bool TP, typename JF>
 __device__ __forceinline__ void probe_tile(const uint2 *tab, int hbits, int wbits, uint32_t wmask,
                                            const uint32_t (&e)[U], const bool (&val)[U],
                                            const int (&fwij)[U], const uint32_t (&fm0)[U],
@@ -233,7 +233,8 @@ __device__ __forceinline__ void probe_tile(const uint2 *tab, int hbits, int wbit
                                            const JF &jparams, const uint2 *ent_sm, const uint32_t *ent_mx,
                                            uint32_t *ent_ck, const uint8_t *lut, int W, int si, const GraphDesc &G,
                                            int32_t r, uint32_t emask, unsigned long long &c9,
-                                           bool (&hit)[U], bool (&mhit)[U], uint32_t (&po)[U]) {
+                                           bool (&hit)[U], bool (&mhit)[U], uint32_t (&po)[U],
+                                           unsigned long long *tp) {
     const uint4 *tq = reinterpret_cast<const uint4 *>(tab);
     const uint32_t nbm1 = (1u << (hbits - 1)) - 1;
     const uint32_t kmask = ~wmask;
@@ -324,6 +325,14 @@ __device__ __forceinline__ void probe_tile(const uint2 *tab, int hbits, int wbit
                 const uint32_t m7 = region_mask(si, J.sj, (int)sm[u].x, J.wij, wik, wjk, g);
                 if (m7 != kMaskCommonVertex) po[u] = lut[m7];
                 else n9++;
+                if (TP) {
+                    // per-hyperedge counts by pattern (rank-ordered rows of 21): the hashed
+                    // hyperedge, the partner (segment) and the third one
+                    const uint32_t p = m7 != kMaskCommonVertex ? (uint32_t)lut[m7] : kPatternCommonVertex;
+                    atomicAdd(&tp[(int64_t)r * 21 + p], 1ull);
+                    atomicAdd(&tp[(int64_t)J.jr * 21 + p], 1ull);
+                    atomicAdd(&tp[(int64_t)(e[u] >> wbits) * 21 + p], 1ull);
+                }
             }
         }
     }
@@ -421,7 +430,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // omegas omega_jr (segment), omega_jk (hashed entry), omega_rk (streamed
 // entry), and g = popcount(Omega_jr & Omega_jk) over e_j's member
 // positions; the region table is invariant under relabelling.
-template <int CAP, int JP, bool PER_EDGE, bool PER_WEDGE, bool MID>
+template <int CAP, int JP, bool PER_EDGE, bool PER_WEDGE, bool MID, bool TP = false>
 __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
     static_assert(JP <= kBlock, "one thread per partner");
     // partner-list entries per lane per step: fewer registers for the short
@@ -663,7 +672,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                 const uint32_t m2 = W > 2 ? seg_mask[qd * kMaskWordsMax + 2] : 0u;
                 const uint32_t m3 = W > 3 ? seg_mask[qd * kMaskWordsMax + 3] : 0u;
                 const bool fastd = (W == 1) && (si > wd) && (sjd > wd);
-                const int32_t jr = (W == 0) ? seg_rank(qd) : 0;
+                const int32_t jr = (W == 0 || TP) ? seg_rank(qd) : 0;
                 const JParams Jd{sjd, wd, fastd, m0, m1, m2, m3, jr};
                 bool hit[kU], mhit[kU];
                 uint32_t po[kU];
@@ -676,8 +685,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                     fm0[u] = m0;
                     ffast[u] = fastd;
                 }
-                probe_tile<kU, PER_EDGE>(tab, hbits, wbits, wmask, entA, valA, fwij, fm0, ffast, [&](int) { return Jd; },
-                                     ent_sm, ent_mx, ent_ck, lut, W, si, G, r, A.emask, c9, hit, mhit, po);
+                probe_tile<kU, PER_EDGE, TP>(tab, hbits, wbits, wmask, entA, valA, fwij, fm0, ffast, [&](int) { return Jd; },
+                                     ent_sm, ent_mx, ent_ck, lut, W, si, G, r, A.emask, c9, hit, mhit, po, A.tp);
                 bool other = false;
 #pragma unroll
                 for (int u = 0; u < kU; u++) {
@@ -805,11 +814,11 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                     J.m1 = W > 1 ? seg_mask[qq * kMaskWordsMax + 1] : 0u;
                     J.m2 = W > 2 ? seg_mask[qq * kMaskWordsMax + 2] : 0u;
                     J.m3 = W > 3 ? seg_mask[qq * kMaskWordsMax + 3] : 0u;
-                    J.jr = (W == 0) ? seg_rank(qq) : 0;
+                    J.jr = (W == 0 || TP) ? seg_rank(qq) : 0;
                     return J;
                 };
-                probe_tile<kU, PER_EDGE>(tab, hbits, wbits, wmask, entA, valA, fwij, fm0, ffast, jf, ent_sm, ent_mx, ent_ck,
-                                     lut, W, si, G, r, A.emask, c9, hit, mhit, po);
+                probe_tile<kU, PER_EDGE, TP>(tab, hbits, wbits, wmask, entA, valA, fwij, fm0, ffast, jf, ent_sm, ent_mx, ent_ck,
+                                     lut, W, si, G, r, A.emask, c9, hit, mhit, po, A.tp);
                 bool other = false;
 #pragma unroll
                 for (int u = 0; u < kU; u++) {
@@ -1033,8 +1042,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_close(CloseArgs A) {
                 J.jr = (int32_t)(jent >> wbits);
                 return J;
             };
-            probe_tile<kU, PER_EDGE>(Wl.tab, hbits, wbits, wmask, ent4, val4, fwij, fm0, ffast, jf, Wl.ent_sm, Wl.ent_mx,
-                                 Wl.ent_ck, lut, W, si, G, r, A.emask, c9, hit, mhit, po);
+            probe_tile<kU, PER_EDGE, TP>(Wl.tab, hbits, wbits, wmask, ent4, val4, fwij, fm0, ffast, jf, Wl.ent_sm, Wl.ent_mx,
+                                 Wl.ent_ck, lut, W, si, G, r, A.emask, c9, hit, mhit, po, A.tp);
             bool other = false;
 #pragma unroll
             for (int u = 0; u < kU; u++) {
@@ -1256,6 +1265,18 @@ struct CloseVariants {
                   : (pw ? occ_blocks<CAP, JP, false, true, MID>() : occ_blocks<CAP, JP, false, false, MID>());
     }
     static void launch(bool pe, bool pw, const CloseArgs &a, int nb, hipStream_t s) {
+        if (a.tp) {
+            // SparseTTT with per-pattern per-hyperedge counts: its own instance (default
+            // configuration only), so that the other closures carry none of its code
+            if constexpr (CAP == 512 && JP == 256) {
+                if (pe || pw) fail(HTRI_E_INVALID, "per-pattern counts of the closure take no per-edge or per-wedge output");
+                hipLaunchKernelGGL((k_close<CAP, JP, false, false, MID, true>), dim3(nb), dim3(kBlock), 0, s, a);
+                HTRI_LAUNCH_CHECK();
+            } else {
+                fail(HTRI_E_INVALID, "per-pattern counts of the closure run the default configuration only");
+            }
+            return;
+        }
         if (pe && pw) hipLaunchKernelGGL((k_close<CAP, JP, true, true, MID>), dim3(nb), dim3(kBlock), 0, s, a);
         else if (pe) hipLaunchKernelGGL((k_close<CAP, JP, true, false, MID>), dim3(nb), dim3(kBlock), 0, s, a);
         else if (pw) hipLaunchKernelGGL((k_close<CAP, JP, false, true, MID>), dim3(nb), dim3(kBlock), 0, s, a);
@@ -1618,6 +1639,7 @@ struct WinArgs {
     unsigned long long *block_part; // each block's pattern counts [blocks][21], summed afterwards
     unsigned long long *stats;      // [0] bitmap words read, [1] hits enumerated
     uint32_t *cwj, *cwjm, *cwkm;
+    unsigned long long *tp;         // as CloseArgs::tp (null: not kept)
 };
 
 // dynamic shared memory: BR, PR and max_classes class rows of nwords words
@@ -1779,6 +1801,11 @@ __global__ __launch_bounds__(kBlock, 6) void k_close_window(WinArgs A) {
             if (((A.emask >> 31) & 1u) && g > 0) return false;
             const uint32_t p = A.lut[region_mask(si, sj, sk, wij, wik, wjk, g)];
             atomicAdd(&cnt[p], 1ull);
+            if (A.tp) {
+                atomicAdd(&A.tp[(int64_t)r * 21 + p], 1ull);
+                atomicAdd(&A.tp[(int64_t)j * 21 + p], 1ull);
+                atomicAdd(&A.tp[(int64_t)k * 21 + p], 1ull);
+            }
             enumerated++;
             const bool counted = PER_EDGE && ((A.emask >> p) & 1u);
             if (counted) atomicAdd(&A.cwkm[base + pr], 1u);
@@ -1947,7 +1974,7 @@ WindowPlan choose_window(Graph &g, uint32_t flags) {
 }
 
 void close_window(Graph &g, const WindowPlan &w, uint32_t emask, const uint8_t *lut_dev, unsigned long long *counts,
-                  unsigned long long *stats, uint32_t *cwj, uint32_t *cwjm, uint32_t *cwkm) {
+                  unsigned long long *stats, uint32_t *cwj, uint32_t *cwjm, uint32_t *cwkm, unsigned long long *tp) {
     if (w.nrows == 0) return;
     hipStream_t s = g.stream;
     Allocator &A = g.al;
@@ -1979,6 +2006,7 @@ void close_window(Graph &g, const WindowPlan &w, uint32_t emask, const uint8_t *
     a.cwj = cwj;
     a.cwjm = cwjm;
     a.cwkm = cwkm;
+    a.tp = tp;
     const bool pe = cwjm != nullptr, pw = cwj != nullptr;
     int nb = 0;
     hipError_t oe;
@@ -2325,7 +2353,8 @@ void closure_stream_stats(Graph &g) {
     g.cstats[7] = (int64_t)h[1];
 }
 
-void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21], uint64_t *t_dev, uint32_t *cw_dev) {
+void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21], uint64_t *t_dev, uint32_t *cw_dev,
+                    unsigned long long *tp_rank) {
     hipStream_t s = g.stream;
     Allocator &A = g.al;
     const int64_t m = g.m;
@@ -2428,7 +2457,10 @@ void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21],
     a.tedge = mid && pe ? tsum.p : nullptr;
     DBuf<unsigned long long> wpart(A, (int64_t)nblocks * (kBlock / kWave) * 21);
     a.wave_part = wpart.p;
-    close_window(g, win, a.emask, lut.p, ctr.p + 1, ctr.p + 26, cw_dev, pe ? cwjm.p : nullptr, pe ? cwkm.p : nullptr);
+    // per-pattern per-hyperedge counts are kept for SparseTTT counting only
+    a.tp = (flags & HTRI_COUNT_SPARSE_TTT) ? tp_rank : nullptr;
+    close_window(g, win, a.emask, lut.p, ctr.p + 1, ctr.p + 26, cw_dev, pe ? cwjm.p : nullptr, pe ? cwkm.p : nullptr,
+                 a.tp);
     HTRI_HIP(hipEventRecord(ew, s));
     launch_close_kernel(cfg, pe, pw, a, nblocks, s, mid);
     HTRI_HIP(hipEventRecord(e2, s));

@@ -347,6 +347,8 @@ struct CloseArgs {
     unsigned long long *tedge;      // middle-centric with per-edge counts: per-hyperedge totals by
                                     // rank, to which each item adds its middle's j-role counts and
                                     // its hashed entries' k-role counts (cwkm is left to the window)
+    unsigned long long *tp = nullptr;          // SparseTTT counting with per-pattern per-hyperedge
+                                               // counts: rows of 21 by rank, three atomics per hit
     unsigned long long *wave_part = nullptr;   // single-graph launches: each wave's pattern counts,
                                                // [waves][21], summed afterwards in a fixed order
                                                // (null: each wave adds its counts per graph)
@@ -397,7 +399,8 @@ struct WindowPlan {
 };
 WindowPlan choose_window(Graph &g, uint32_t flags);
 void close_window(Graph &g, const WindowPlan &w, uint32_t emask, const uint8_t *lut_dev, unsigned long long *counts,
-                  unsigned long long *stats, uint32_t *cwj, uint32_t *cwjm, uint32_t *cwkm);
+                  unsigned long long *stats, uint32_t *cwj, uint32_t *cwjm, uint32_t *cwkm,
+                  unsigned long long *tp = nullptr);
 // mid: middle-centric items (default configuration only)
 int close_blocks_per_cu(const CloseConfig &cfg, bool pe, bool pw, bool mid = false);
 void launch_close_kernel(const CloseConfig &cfg, bool pe, bool pw, const CloseArgs &a, int nblocks, hipStream_t s,
@@ -411,8 +414,10 @@ void count_inclusion_classes(Graph &g, uint32_t mask, int64_t counts[21], uint64
                              unsigned long long *tp_rank = nullptr /* m*21, rank order, accumulated */);
 // every hyperwedge closed, the triangles of pattern target listed
 void enumerate_all_wedges(Graph &g, int target, int64_t capacity, int32_t *dev_out, unsigned long long *dev_found);
+// tp_rank (SparseTTT only, or null): per-pattern counts of every hyperedge,
+// rows of 21 by rank, added to
 void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21], uint64_t *t_dev /*m or null*/,
-                    uint32_t *cw_dev /*nw or null*/);
+                    uint32_t *cw_dev /*nw or null*/, unsigned long long *tp_rank = nullptr);
 // fill the S entries of the last count's census (run on request)
 void closure_stream_stats(Graph &g);
 // subgraph.hip: the sub-hypergraph of sigma-sampling (kept: normalised ids

@@ -8,8 +8,8 @@
 //   * patterns 1-8: the search around the inclusion hyperwedges (Count-CCC,
 //     Count-TCC, Count-TTC), one atomic per hyperedge of each triangle;
 //   * patterns 10-16: the thick-pair scan of Count-DenseTTT, the same way;
-//   * patterns 17-20: the SparseTTT closure, one pattern per pass, its
-//     per-hyperedge counts restricted to that pattern;
+//   * patterns 17-20: one SparseTTT closure, each hit without a common
+//     vertex adding to its three hyperedges' counts of its pattern;
 //   * pattern 9, the common-vertex pattern that holds most triangles: the
 //     remainder, all patterns minus the other nineteen.
 #include <algorithm>
@@ -20,26 +20,20 @@
 namespace htri {
 namespace {
 
-// out[x][p] (normalised ids) from the rank-ordered partial counts, the
-// per-pattern sparse counts (normalised ids) and the all-pattern counts
-__global__ void k_assemble(const unsigned long long *tr, const int64_t *t_all, const int64_t *ts17,
-                           const int64_t *ts18, const int64_t *ts19, const int64_t *ts20, const int32_t *norm_of_rank,
+// out[x][p] (normalised ids) from the rank-ordered partial counts and the
+// all-pattern counts (normalised ids): pattern 9 is the remainder
+__global__ void k_assemble(const unsigned long long *tr, const int64_t *t_all, const int32_t *norm_of_rank,
                            int64_t m, int64_t *out) {
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
         const int64_t x = norm_of_rank[r];
         int64_t *o = out + x * 21;
         const unsigned long long *q = tr + r * 21;
         int64_t rest = 0;
-        for (int p = 1; p <= 16; p++) {
+        for (int p = 1; p <= 20; p++) {
             if (p == 9) continue;
             o[p] = (int64_t)q[p];
             rest += o[p];
         }
-        o[17] = ts17 ? ts17[x] : 0;
-        o[18] = ts18 ? ts18[x] : 0;
-        o[19] = ts19 ? ts19[x] : 0;
-        o[20] = ts20 ? ts20[x] : 0;
-        rest += o[17] + o[18] + o[19] + o[20];
         o[0] = t_all[x];
         o[9] = t_all[x] - rest;
     }
@@ -79,15 +73,12 @@ void count_per_edge_patterns(Graph &g, int64_t counts[21], int64_t *dev_out) {
     int64_t tmp[21];
     if (any18) count_inclusion_classes(g, 0x1FEu, tmp, nullptr, 0, 0, nullptr, nullptr, tr.p);
     if (any1016) count_dense_ttt(g, true, tmp, nullptr, tr.p);
-    DBuf<int64_t> ts[4];
-    for (int p = 17; p <= 20; p++) {
-        if (c[p] <= 0) continue;
-        ts[p - 17].alloc(A, std::max<int64_t>(m, 1));
-        count_patterns(g, 1u << p, HTRI_COUNT_SPARSE_TTT, tmp, (uint64_t *)ts[p - 17].p, nullptr);
-    }
+    bool any1720 = false;
+    for (int p = 17; p <= 20; p++) any1720 |= c[p] > 0;
+    if (any1720) count_patterns(g, 0x1E0000u, HTRI_COUNT_SPARSE_TTT, tmp, nullptr, nullptr, tr.p);
     if (m > 0) {
-        hipLaunchKernelGGL(k_assemble, dim3(grid_for(m, 256)), dim3(256), 0, s, tr.p, t_all.p, ts[0].p, ts[1].p,
-                           ts[2].p, ts[3].p, g.norm_of_rank.p, m, dev_out);
+        hipLaunchKernelGGL(k_assemble, dim3(grid_for(m, 256)), dim3(256), 0, s, tr.p, t_all.p, g.norm_of_rank.p, m,
+                           dev_out);
         HTRI_LAUNCH_CHECK();
     }
     HTRI_HIP(hipStreamSynchronize(s));

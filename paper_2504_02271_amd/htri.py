@@ -329,9 +329,17 @@ class Graph:
                "htri_count_patterns", self._h)
         return counts, pe, pw
 
-    def count_per_edge_patterns(self):
-        """(counts int64[21], per-hyperedge per-pattern counts int64[m, 21])."""
+    def count_per_edge_patterns(self, device_out: bool = False):
+        """(counts int64[21], per-hyperedge per-pattern counts int64[m, 21]);
+        device_out: the per-hyperedge counts as a torch tensor on the GPU."""
         counts = np.zeros(21, np.int64)
+        if device_out:
+            import torch
+            out = torch.empty((max(self.num_edges, 1), 21), dtype=torch.int64, device="cuda")
+            _check(self._lib.htri_count_per_edge_patterns(self._h, _ptr(counts), out.data_ptr(),
+                                                          HTRI_OUTPUT_ON_DEVICE),
+                   "htri_count_per_edge_patterns", self._h)
+            return counts, out[: self.num_edges]
         out = np.zeros((max(self.num_edges, 1), 21), np.int64)
         _check(self._lib.htri_count_per_edge_patterns(self._h, _ptr(counts), _ptr(out), 0),
                "htri_count_per_edge_patterns", self._h)
