@@ -172,16 +172,42 @@ __global__ __launch_bounds__(256) void k_forward(const float *params, const floa
 __global__ __launch_bounds__(256) void k_score(FeatArgs A, const float *params, const int64_t *wedges, int64_t n,
                                                double *score) {
     __shared__ float P[kNumParams];
+    __shared__ int64_t s_own[2];
     for (int t = threadIdx.x; t < kNumParams; t += blockDim.x) P[t] = params[t];
     __syncthreads();
-    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t e = wedges ? wedges[u] : u;
-        const int64_t r = owner_of_f(A.fptr, A.m, e);
+    auto score_one = [&](int64_t u, int64_t e, int64_t r) {
         float f[kIn];
         wedge_features(A, r, e, f);
         float s = mlp_forward_row(P, f);
         s = fminf(fmaxf(s, 0.f), 30.f);
         score[u] = (double)expm1f(s);
+    };
+    if (wedges) {
+        // listed wedges (a candidate pool): each owner by binary search over all owners
+        for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t e = wedges[u];
+            score_one(u, e, owner_of_f(A.fptr, A.m, e));
+        }
+        return;
+    }
+    // every wedge: the block takes 256 consecutive ones, whose owners lie between
+    // the owners of its first and last (found once), and each thread searches only there
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+        if (threadIdx.x == 0) {
+            s_own[0] = owner_of_f(A.fptr, A.m, base);
+            s_own[1] = owner_of_f(A.fptr, A.m, min(base + (int64_t)blockDim.x, n) - 1);
+        }
+        __syncthreads();
+        const int64_t u = base + threadIdx.x;
+        if (u < n) {
+            int64_t lo = s_own[0], hi = s_own[1] + 1;
+            while (hi - lo > 1) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (A.fptr[mid] <= u) lo = mid; else hi = mid;
+            }
+            score_one(u, u, lo);
+        }
+        __syncthreads();   // s_own is rewritten for the next chunk
     }
 }
 
