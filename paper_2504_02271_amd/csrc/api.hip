@@ -182,8 +182,6 @@ htri_status htri_clear_wedges(htri_graph *h) {
         g.mptr.reset();
         g.fmask.reset();
         g.indeg.reset();
-        g.inpos.reset();
-        g.insnap.reset();
         g.incl_pos.reset();
         g.incl_pairs.reset();
         g.n_incl_pairs = 0;

@@ -274,8 +274,6 @@ void drop_step1(Graph &g) {
     g.mptr.reset();
     g.fmask.reset();
     g.indeg.reset();
-    g.inpos.reset();
-    g.insnap.reset();
     g.incl_pos.reset();
     g.incl_pairs.reset();
     g.n_incl_pairs = 0;

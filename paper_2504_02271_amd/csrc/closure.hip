@@ -1340,52 +1340,6 @@ GraphDesc graph_desc(const Graph &g) {
 
 namespace {
 
-// number of in-list entries of each middle j: all its earlier neighbours
-// below the window start w0, else (j >= w0) the snapshot of its count taken
-// when the owners below w0 were done
-__global__ void k_inlist_counts(const uint32_t *indeg, const uint32_t *snap, int64_t top0, int64_t w0, int64_t m,
-                                int64_t *cnt) {
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += (int64_t)gridDim.x * blockDim.x)
-        cnt[j] = j < w0 ? (int64_t)indeg[j] : (int64_t)snap[j - top0];
-}
-
-// scatter every hyperwedge (r, j), r < owner_end, to j's in-list at its slot
-// (one InEntry, see the header); one wave per owner.  A slot outside j's
-// range sets *bad instead.
-__global__ void k_inlist_fill(const int64_t *fptr, const uint32_t *fadj, int wbits, int64_t owner_end,
-                              const int32_t *esize, const int64_t *eptr, const int32_t *emem, const int64_t *mptr,
-                              const uint32_t *fmask, const int64_t *iptr, const uint32_t *inpos, uint4 *inl,
-                              unsigned int *bad) {
-    const uint32_t wmask = (1u << wbits) - 1;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
-    for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; r < owner_end; r += nwaves) {
-        const int64_t b = fptr[r], e = fptr[r + 1];
-        const int sr = esize[r];
-        const int Wr = mask_words(sr);
-        const int64_t mb = mptr[r], rb = eptr[r];
-        for (int64_t q = b + lane; q < e; q += kWave) {
-            const uint32_t ent = fadj[q];
-            const uint32_t j = ent >> wbits, om = ent & wmask;
-            uint32_t v = kInNoVertex;
-            if (om == 1u && Wr > 0) {
-                const int64_t mo = mb + (q - b) * Wr;
-                for (int w = 0; w < Wr; w++) {
-                    const uint32_t x = fmask[mo + w];
-                    if (x) v = (uint32_t)emem[rb + w * 32 + __ffs(x) - 1];
-                }
-            }
-            const int64_t slot = iptr[j] + inpos[q];
-            if (slot < iptr[j + 1]) {
-                inl[slot] = make_uint4((uint32_t)q, ((uint32_t)(e - q - 1) << wbits) | om, v,
-                                       ((uint32_t)r << wbits) | (uint32_t)sr);
-            } else {
-                atomicOr(bad, 1u);
-            }
-        }
-    }
-}
-
 // Middle-centric work items per middle j (at least one forward entry and one
 // in-list entry): wcnt = 1 for a middle closed by one wave (at most
 // kWaveMidHashMax forward entries, at most kWaveOwnerMax in-list entries, at
@@ -1476,52 +1430,6 @@ void build_items(Graph &g, int32_t gid, const CloseConfig &cfg, ItemLists &out, 
                            cfg.jp, gid, icnt.p, wcnt.p, out.block.p, out.wave.p);
         HTRI_LAUNCH_CHECK();
     });
-}
-
-int64_t inlist_bytes(Graph &g, int64_t owner_end) {
-    const int64_t n = owner_end > 0 ? read_i64(g.fptr.p + owner_end, g.stream) : 0;
-    // one 16-byte entry per hyperwedge, offsets and counts, item counts
-    return n * 16 + (g.m + 1) * 40;
-}
-
-// The in-list for owners below owner_end (m, or one of the window's
-// possible starts).
-void build_inlist(Graph &g, int64_t owner_end, InList &out) {
-    hipStream_t s = g.stream;
-    Allocator &A = g.al;
-    const int64_t m = g.m;
-    const int64_t n = owner_end > 0 ? read_i64(g.fptr.p + owner_end, s) : 0;
-    if (n >= (int64_t)UINT32_MAX) fail(HTRI_E_UNSUPPORTED, "in-list beyond 2^32 hyperwedges");
-    int snap = -1;
-    if (owner_end < m)
-        for (int k = 0; k < kWindowStarts; k++)
-            if (window_start(m, k) == owner_end) snap = k;
-    if (owner_end < m && snap < 0) fail(HTRI_E_UNSUPPORTED, "in-list for a window start the builder did not mark");
-    const int64_t top0 = g.insnap_top;
-    if (2 * g.wbits > 32) fail(HTRI_E_UNSUPPORTED, "in-list packing needs hyperedge sizes below 2^16");
-    out.n = n;
-    out.inl.alloc(A, n);
-    out.iptr.alloc(A, m + 1);
-    if (m > 0) {
-        hipLaunchKernelGGL(k_inlist_counts, dim3(grid_for(m, 256)), dim3(256), 0, s, g.indeg.p,
-                           snap >= 0 ? g.insnap.p + (int64_t)snap * (m - top0) : g.insnap.p, top0, owner_end, m,
-                           out.iptr.p);
-        HTRI_LAUNCH_CHECK();
-    }
-    scan_exclusive_i64(A, out.iptr.p, out.iptr.p, m, out.iptr.p + m, s);
-    if (read_i64(out.iptr.p + m, s) != n) fail(HTRI_E_DEVICE, "in-list counts do not add up to the hyperwedges");
-    if (n > 0) {
-        DBuf<unsigned int> bad(A, 1);
-        fill_u32(bad.p, 1, 0, s);
-        hipLaunchKernelGGL(k_inlist_fill, dim3(grid_for(owner_end * kWave, 256, 16384)), dim3(256), 0, s, g.fptr.p,
-                           g.fadj.p, g.wbits, owner_end, g.esize.p, g.eptr.p, g.emem.p, g.mptr.p, g.fmask.p,
-                           out.iptr.p, g.inpos.p, out.inl.p, bad.p);
-        HTRI_LAUNCH_CHECK();
-        unsigned int hb = 0;
-        HTRI_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(hb), hipMemcpyDeviceToHost, s));
-        HTRI_HIP(hipStreamSynchronize(s));
-        if (hb) fail(HTRI_E_DEVICE, "in-list slot outside its middle's range");
-    }
 }
 
 void build_items_mid(Graph &g, int32_t gid, const CloseConfig &cfg, const InList &in, ItemLists &out) {
@@ -2377,7 +2285,7 @@ void count_patterns(Graph &g, uint32_t mask, uint32_t flags, int64_t counts[21],
         size_t free_b = 0, total_b = 0;
         const int64_t n_in = read_i64(g.fptr.p + owner_end, s);
         mid_wedges = n_in;
-        if (n_in >= (int64_t)UINT32_MAX) mid = false;
+        if (n_in > 0 && !transpose_fits(m, n_in)) mid = false;
         else if (hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
                  (double)inlist_bytes(g, owner_end) > 0.9 * (double)free_b)
             mid = false;

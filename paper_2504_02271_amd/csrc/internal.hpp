@@ -248,8 +248,9 @@ struct Graph {
     DBuf<int32_t> vadj;
     DBuf<int32_t> vpos;         // membership -> its position inside E_v
 
-    // a graph of a batch: counted by probing around the owner only, so step 1
-    // keeps no in-list slots and no per-window-start snapshots
+    // a graph of a batch: counted by probing around the owner only; step 1
+    // counts its in-degrees with one atomic per hyperwedge, inside the
+    // captured launch sequence
     bool batch_member = false;
 
     // step 1: forward adjacency N+(r), sorted by rank
@@ -262,12 +263,6 @@ struct Graph {
     DBuf<int64_t> mptr;         // m+1, offsets (in 32-bit words) of Omega masks
     DBuf<uint32_t> fmask;
     DBuf<uint32_t> indeg;       // earlier neighbours of each hyperedge
-    // slot of each hyperwedge (r, j) among j's earlier neighbours: the owners
-    // are counted in rank ranges split at the dense window's possible starts,
-    // so the owners before any such start hold j's first slots
-    DBuf<uint32_t> inpos;
-    DBuf<uint32_t> insnap;      // kWindowStarts snapshots of indeg over ranks [insnap_top, m)
-    int64_t insnap_top = 0;
     int64_t summary[6] = {0, 0, 0, 0, 0, 0};
     // inclusion hyperwedges for the class-split sampler (built on first use):
     // their positions ascending, and (end, other end) pairs of ranks, both
@@ -383,8 +378,18 @@ struct InList {
     DBuf<int64_t> iptr;
     int64_t n = 0;
 };
+// transpose.hip: the later ends' side of the forward adjacency, bucketed by
+// rank (no device atomic per hyperwedge).  It takes graphs of at most 2^28
+// hyperedges and fewer than 2^32 hyperwedges (n: those of the owners
+// covered).
+bool transpose_fits(int64_t m, int64_t n);
+// indeg[j] += earlier neighbours of j over all n hyperwedges; n_incl and
+// max_omega receive the inclusion count and the largest omega
+void count_later_ends(Graph &g, int64_t n, unsigned int *indeg, unsigned long long *n_incl,
+                      unsigned int *max_omega);
 // device bytes build_inlist needs at its peak
 int64_t inlist_bytes(Graph &g, int64_t owner_end);
+// HTRI_E_UNSUPPORTED beyond transpose_fits()
 void build_inlist(Graph &g, int64_t owner_end, InList &out);
 // middle-centric work items of one graph
 void build_items_mid(Graph &g, int32_t gid, const CloseConfig &cfg, const InList &in, ItemLists &out);
