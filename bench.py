@@ -387,8 +387,15 @@ def main() -> int:
     G = htri.graph_load(g.offsets, g.members, g.num_vertices)
     torch.cuda.synchronize()
     load_ms = (time.time() - t0) * 1e3
-    log(f"[bench] loaded + normalised on the GPU in {load_ms:.1f} ms (incl. host-to-device copy); "
-        f"{G.num_edges} hyperedges kept, {G.removed} duplicates removed")
+    # the same load again, with the caching allocator's blocks already mapped
+    t0 = time.time()
+    G2 = htri.graph_load(g.offsets, g.members, g.num_vertices)
+    torch.cuda.synchronize()
+    load_warm_ms = (time.time() - t0) * 1e3
+    G2.close()
+    del G2
+    log(f"[bench] loaded + normalised on the GPU in {load_ms:.1f} ms (incl. host-to-device copy; "
+        f"{load_warm_ms:.1f} ms a second time); {G.num_edges} hyperedges kept, {G.removed} duplicates removed")
 
     if args.copy_calibration_mib > 0:
         nb = args.copy_calibration_mib << 20
@@ -525,6 +532,7 @@ def main() -> int:
             "hyperedges": G.num_edges,
             "connected_triples_W": int(s[3]),
             "load_normalise_ms_incl_h2d": round(load_ms, 2),
+            "load_normalise_ms_incl_h2d_second_load": round(load_warm_ms, 2),
             "stage_ms": {"wedges": float(stage_ms[:, 0].mean()), "schedule": float(stage_ms[:, 1].mean()),
                          "closure": close_ms, "closure_window": win_ms, "closure_probing": probe_ms,
                          "reduce": float(stage_ms[:, 3].mean())},

@@ -26,7 +26,11 @@
 namespace htri {
 namespace {
 
-constexpr int kTrBlock = 256;
+// hist and scatter: 512 blocks of 1024 threads at most.  Each block keeps one
+// partly written line per bucket (two for the in-list) open in its XCD's L2;
+// fewer, larger blocks keep fewer open lines, so more of them fill before
+// they are written back.
+constexpr int kTrBlock = 1024, kTrGridMax = 512;
 constexpr int kTrCountBlock = 1024;   // counting and placing blocks hold 64-128 KB of LDS: 16 waves each
 // entries of one bucket per counting block, and per placing block: a placing
 // block reserves its share of each later end's range with one atomic, so it
@@ -321,7 +325,7 @@ void bucket_hyperwedges(Graph &g, int64_t owner_end, int64_t n, int shift_min, B
     out.bk = buckets_for(g.m, shift_min);
     const int nb = (int)out.bk.nb;
     const int G = (int)grid_for(owner_end * kWave, kTrBlock,
-                                std::max<int64_t>(256, std::min<int64_t>(2048, (1 << 22) / nb)));
+                                std::max<int64_t>(256, std::min<int64_t>(kTrGridMax, (1 << 22) / nb)));
     out.G = G;
     const size_t lds = sizeof(uint32_t) * (size_t)nb;
     DBuf<uint32_t> hist(A, (size_t)nb * G);
