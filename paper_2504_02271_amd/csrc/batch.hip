@@ -588,7 +588,6 @@ htri_status htri_batch_load(int32_t count, const int64_t *const *edge_offsets, c
             auto G = std::make_unique<Graph>();
             G->stream = B->stream;
             G->al.stream = B->stream;
-            G->batch_member = true;
             try {
                 graph_load(*G, edge_offsets[g], num_edges[g], members[g], num_vertices[g], flags);
                 build_wedges(*G);

@@ -248,10 +248,6 @@ struct Graph {
     DBuf<int32_t> vadj;
     DBuf<int32_t> vpos;         // membership -> its position inside E_v
 
-    // a graph of a batch: counted by probing around the owner only; step 1
-    // counts its in-degrees with one atomic per hyperwedge, inside the
-    // captured launch sequence
-    bool batch_member = false;
 
     // step 1: forward adjacency N+(r), sorted by rank
     bool have_wedges = false;

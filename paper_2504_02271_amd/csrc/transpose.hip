@@ -56,7 +56,9 @@ struct Buckets {
 Buckets buckets_for(int64_t m, int shift_min) {
     Buckets b;
     const int bits = bits_for((uint64_t)(m > 0 ? m - 1 : 0));
-    b.shift = std::max(shift_min, bits - 13);
+    // a graph of fewer than 2^shift_min hyperedges is one bucket of its own
+    // width (the counting blocks clear only that many LDS counters)
+    b.shift = std::max(std::min(shift_min, bits), bits - 13);
     b.nb = ((m > 0 ? m : 1) + ((int64_t)1 << b.shift) - 1) >> b.shift;
     return b;
 }
