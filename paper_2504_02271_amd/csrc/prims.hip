@@ -91,10 +91,20 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(const T *in, T *out, i
         *total_out = run;
 }
 
+// total of an empty scan: a kernel rather than a memset node, so that a
+// captured launch sequence holds no memset
+template <typename T>
+__global__ void k_zero_one(T *p) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p = T(0);
+}
+
 template <typename T>
 void scan_exclusive(Allocator &a, const T *in, T *out, int64_t n, T *total, hipStream_t s) {
     if (n <= 0) {
-        if (total) HTRI_HIP(hipMemsetAsync(total, 0, sizeof(T), s));
+        if (total) {
+            hipLaunchKernelGGL(k_zero_one<T>, dim3(1), dim3(64), 0, s, total);
+            HTRI_LAUNCH_CHECK();
+        }
         return;
     }
     int64_t tiles = (n + kScanTile - 1) / kScanTile;

@@ -32,11 +32,12 @@ namespace {
 // they are written back.
 constexpr int kTrBlock = 1024, kTrGridMax = 512;
 constexpr int kTrCountBlock = 1024;   // counting and placing blocks hold 64-128 KB of LDS: 16 waves each
-// entries of one bucket per counting block, and per placing block: a placing
+// entries of one bucket per counting block (fewer on a small graph, so that
+// its few buckets still spread over many blocks), and per placing block: a placing
 // block reserves its share of each later end's range with one atomic, so it
 // takes enough entries per later end to amortise them, while the 16-byte
 // entries it scatters stay within a footprint the L2 can combine
-constexpr uint32_t kChunkCount = 262144, kChunkPlace = 65536;
+constexpr uint32_t kChunkCountMax = 262144, kChunkCountMin = 4096, kChunkPlace = 65536;
 // ranks per bucket: 2^15 for the in-degrees (the scatter writes 2-byte
 // offsets only; fewer buckets give longer runs per block), 2^14 for the
 // in-list (its placing blocks hold 2^shift LDS counters)
@@ -129,19 +130,33 @@ __global__ __launch_bounds__(kTrBlock) void k_tr_hist(const int64_t *fptr, const
             if (valid && h == lane) atomicAdd(&sh[bkt], (uint32_t)len);
         }
     }
+    __shared__ unsigned long long s_inc;
+    __shared__ unsigned int s_mx;
     if (STATS) {
+        if (threadIdx.x == 0) {
+            s_inc = 0;
+            s_mx = 0;
+        }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             inc += __shfl_xor(inc, o, 64);
             const unsigned int x = __shfl_xor(mx, o, 64);
             mx = x > mx ? x : mx;
         }
-        if (lane == 0) {
-            if (inc) atomicAdd(n_incl, inc);
-            if (mx) atomicMax(max_omega, mx);
-        }
     }
     __syncthreads();
+    if (STATS) {
+        // one pair of device atomics per block, not per wave
+        if (lane == 0) {
+            if (inc) atomicAdd(&s_inc, inc);
+            if (mx) atomicMax(&s_mx, mx);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (s_inc) atomicAdd(n_incl, s_inc);
+            if (s_mx) atomicMax(max_omega, s_mx);
+        }
+    }
     for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[(int64_t)b * gridDim.x + blockIdx.x] = sh[b];
 }
 
@@ -243,11 +258,12 @@ __global__ void k_tr_bucket_starts(const uint32_t *off, int nb, int G, uint32_t 
 // 4: per chunk, LDS counts of its later ends, added to cnt (uint32 or u64)
 template <typename C>
 __global__ __launch_bounds__(kTrCountBlock) void k_tr_count(const uint16_t *tj, const uint32_t *cst, int nb,
-                                                       const uint32_t *bo, int shift, int64_t m, C *cnt) {
+                                                       const uint32_t *bo, uint32_t chunk, int shift, int64_t m,
+                                                       C *cnt) {
     extern __shared__ uint32_t sh[];
     int b;
     uint32_t lo, hi;
-    if (!chunk_range(blockIdx.x, cst, nb, bo, kChunkCount, &b, &lo, &hi)) return;
+    if (!chunk_range(blockIdx.x, cst, nb, bo, chunk, &b, &lo, &hi)) return;
     const int width = 1 << shift;
     for (int i = threadIdx.x; i < width; i += blockDim.x) sh[i] = 0;
     __syncthreads();
@@ -306,7 +322,15 @@ struct Bucketed {
     DBuf<uint16_t> tj;
     DBuf<uint4> te;
     uint32_t ncount = 0, nplace = 0;   // grid bounds: at most one partial chunk per bucket
+    uint32_t chunk_count = kChunkCountMax;
 };
+
+// entries per counting block: about n / 1024, a power of two in [4096, 262144]
+uint32_t count_chunk(int64_t n) {
+    uint32_t c = kChunkCountMin;
+    while (c < kChunkCountMax && (int64_t)c * 1024 < n) c <<= 1;
+    return c;
+}
 
 // chunk table: chunks of at most `chunk` entries per bucket, scanned
 void chunk_table(Allocator &A, const Bucketed &bw, uint32_t chunk, int64_t n, DBuf<uint32_t> &cst, uint32_t *bound,
@@ -346,7 +370,8 @@ void bucket_hyperwedges(Graph &g, int64_t owner_end, int64_t n, int shift_min, B
                        out.tj.p, out.te.p);
     HTRI_LAUNCH_CHECK();
     hist.reset();
-    chunk_table(A, out, kChunkCount, n, out.cst_count, &out.ncount, s);
+    out.chunk_count = count_chunk(n);
+    chunk_table(A, out, out.chunk_count, n, out.cst_count, &out.ncount, s);
     if (PAYLOAD) chunk_table(A, out, kChunkPlace, n, out.cst_place, &out.nplace, s);
 }
 
@@ -368,8 +393,8 @@ void count_later_ends(Graph &g, int64_t n, unsigned int *indeg, unsigned long lo
     bucket_hyperwedges<false, true>(g, g.m, n, kShiftIndeg, bw, n_incl, max_omega);
     const int nb = (int)bw.bk.nb;
     hipLaunchKernelGGL((k_tr_count<unsigned int>), dim3(bw.ncount), dim3(kTrCountBlock),
-                       sizeof(uint32_t) << bw.bk.shift, g.stream, bw.tj.p, bw.cst_count.p, nb, bw.bo.p, bw.bk.shift,
-                       g.m, indeg);
+                       sizeof(uint32_t) << bw.bk.shift, g.stream, bw.tj.p, bw.cst_count.p, nb, bw.bo.p,
+                       bw.chunk_count, bw.bk.shift, g.m, indeg);
     HTRI_LAUNCH_CHECK();
     stream_sync(g.stream);
 }
@@ -413,7 +438,7 @@ void build_inlist(Graph &g, int64_t owner_end, InList &out) {
         DBuf<unsigned long long> cnt(A, m + 1);
         fill_u64((uint64_t *)cnt.p, m + 1, 0, s);
         hipLaunchKernelGGL((k_tr_count<unsigned long long>), dim3(bw.ncount), dim3(kTrCountBlock), lds, s, bw.tj.p,
-                           bw.cst_count.p, nb, bw.bo.p, bw.bk.shift, m, cnt.p);
+                           bw.cst_count.p, nb, bw.bo.p, bw.chunk_count, bw.bk.shift, m, cnt.p);
         HTRI_LAUNCH_CHECK();
         scan_exclusive_i64(A, (const int64_t *)cnt.p, out.iptr.p, m, out.iptr.p + m, s);
     }
