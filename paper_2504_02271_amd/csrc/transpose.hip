@@ -12,12 +12,12 @@
 //   3. scatter: the same blocks visit the same hyperwedges again and write,
 //      run by run, the later end's offset inside its bucket (16 bits) and,
 //      for the in-list, the 16-byte entry.
-//   4. per chunk of at most kChunk entries of one bucket: an LDS histogram of
-//      the offsets, added to each later end's count with one atomic per
-//      (chunk, later end).
+//   4. per chunk of one bucket (about n/1024 entries, 4,096 to 262,144): an
+//      LDS histogram of the offsets, added to each later end's count with one
+//      atomic per (chunk, later end).
 //   5. in-list only: a scan of the counts gives each later end's range; each
-//      chunk reserves its share of every later end's range with one atomic
-//      and places its entries with LDS counters.
+//      chunk of 65,536 entries reserves its share of every later end's range
+//      with one atomic and places its entries with LDS counters.
 // No order is kept inside a later end's group.
 #include <algorithm>
 
