@@ -169,7 +169,9 @@ __global__ __launch_bounds__(256) void k_forward(const float *params, const floa
 
 // features + forward fused over a list of wedges: predicted closure count
 // expm1(max(s, 0)) (s clamped) per wedge
-__global__ __launch_bounds__(256) void k_score(FeatArgs A, const float *params, const int64_t *wedges, int64_t n,
+// five waves per SIMD: the scores wait on the features' dependent gathers, and
+// the row's work (a call, so that the two loops share it) fits 96 VGPRs
+__global__ __launch_bounds__(256, 5) void k_score(FeatArgs A, const float *params, const int64_t *wedges, int64_t n,
                                                double *score) {
     __shared__ float P[kNumParams];
     __shared__ int64_t s_own[2];
