@@ -67,8 +67,7 @@ Buckets buckets_for(int64_t m, int shift_min) {
 // lanes [0, nvalid) of the wave hold entries in bucket order (non-decreasing
 // bucket ids); returns, for this lane, the lane that heads its run, and sets
 // len on a head to the run's length
-__device__ __forceinline__ int run_head(uint32_t bkt, bool valid, int lane, int nvalid, uint64_t *heads_out,
-                                        int *len) {
+__device__ __forceinline__ int run_head(uint32_t bkt, bool valid, int lane, int nvalid, int *len) {
     const uint32_t prev = __shfl_up(bkt, 1, kWave);
     const bool head = valid && (lane == 0 || prev != bkt);
     const uint64_t heads = __ballot(head);
@@ -78,7 +77,6 @@ __device__ __forceinline__ int run_head(uint32_t bkt, bool valid, int lane, int 
         const int nxt = after ? __ffsll((unsigned long long)after) - 1 : nvalid;
         *len = nxt - lane;
     }
-    *heads_out = heads;
     return 63 - __clzll((long long)(heads & upto));
 }
 
@@ -123,10 +121,8 @@ __global__ __launch_bounds__(kTrBlock) void k_tr_hist(const int64_t *fptr, const
                     if (om > mx) mx = om;
                 }
             }
-            uint64_t heads;
             int len = 0;
-            const int h = run_head(bkt, valid, lane, nvalid, &heads, &len);
-            (void)h;
+            const int h = run_head(bkt, valid, lane, nvalid, &len);
             if (valid && h == lane) atomicAdd(&sh[bkt], (uint32_t)len);
         }
     }
@@ -195,9 +191,8 @@ __global__ __launch_bounds__(kTrBlock) void k_tr_scatter(const int64_t *fptr, co
                 ent = fadj[q];
                 bkt = (ent >> wbits) >> shift;
             }
-            uint64_t heads;
             int len = 0;
-            const int h = run_head(bkt, valid, lane, nvalid, &heads, &len);
+            const int h = run_head(bkt, valid, lane, nvalid, &len);
             uint32_t base = 0;
             if (valid && h == lane) base = atomicAdd(&sh[bkt], (uint32_t)len);
             base = __shfl(base, h, kWave);
