@@ -291,15 +291,32 @@ def test_wide_tile_keys(htri):
 
 
 def test_owner_with_many_incidences(htri):
-    """An owner meeting more incidences than an LDS tile holds goes through
-    the global sort: hyperedge 0 (3,000 vertices, no stored mask) owns its
-    hyperwedges in input order; a 1,501-vertex partner gives a large omega
-    and a 101-vertex one uses all four mask words."""
+    """An owner meeting more incidences than an LDS tile holds (4,600) is
+    sorted by a block of its own: hyperedge 0 (3,000 vertices, no stored mask)
+    owns its hyperwedges in input order; a 1,501-vertex partner gives a large
+    omega and a 101-vertex one uses all four mask words."""
     edges = [list(range(3000)), list(range(0, 3000, 2)) + [3000], list(range(100)) + [5000]]
     edges += [[i, 3001 + (i % 50)] for i in range(3000)]
     g = synth.from_lists(edges, 5001, "many-incidences")
     for flags in (htri.HTRI_DEDUPE_EDGES | htri.HTRI_ORDER_INPUT, htri.HTRI_DEDUPE_EDGES):
         check_exact(htri, g, flags=flags)
+
+
+def test_owners_on_both_sides_of_the_block_limit(htri):
+    """Large owners in one graph on both sides of the 16,384 incidences one
+    block sorts in LDS, in input order: hyperedge 0 (22,120 incidences) goes
+    through the global sort, hyperedge 1 (10,311, no stored mask) and
+    hyperedge 3 (3,120, 120 vertices: four mask words) through the block
+    sort, hyperedge 2 (600) through a tile; then the same graph ordered by
+    delta, and with the 64-bit keys that send every large owner to the
+    global sort."""
+    edges = [list(range(3000)), list(range(0, 3000, 2)) + [5000], list(range(100)) + [5000], list(range(100, 220))]
+    edges += [[i, 3000 + (7 * i + 13 * c) % 2000] for i in range(3000) for c in range(6)]
+    edges += [[i, 3000 + (7 * i + 13 * c) % 2000] for i in range(100, 220) for c in range(6, 26)]
+    g = synth.from_lists(edges, 5001, "block-limit")
+    d = htri.HTRI_DEDUPE_EDGES
+    for flags in (d | htri.HTRI_ORDER_INPUT, d, d | htri.HTRI_ORDER_INPUT | htri.HTRI_WIDE_TILE_KEYS):
+        check_exact(htri, g, flags=flags, windows=("off", "auto"))
 
 
 @pytest.mark.parametrize("name", ["small0", "small5", "small9", "small11", "tiny", "clique", "coauth"])
