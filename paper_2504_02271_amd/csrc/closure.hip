@@ -1502,8 +1502,7 @@ __device__ __forceinline__ void block_popcount_prefix(const uint32_t *x, int n, 
 // one block per window row; dynamic shared memory: two rows of nwords words
 // and their prefix
 __global__ __launch_bounds__(256) void k_window_rows(const int64_t *fptr, const uint32_t *fadj, int wbits, int64_t w0,
-                                                     int nwords, uint32_t *bf, uint32_t *bf1, uint32_t *bi1,
-                                                     uint32_t *pf) {
+                                                     int nwords, uint32_t *bf, uint32_t *bf1, uint32_t *pf) {
     extern __shared__ uint32_t dyn[];
     uint32_t *rf = dyn, *r1 = dyn + nwords;
     int32_t *pre = (int32_t *)(dyn + 2 * nwords);
@@ -1518,10 +1517,7 @@ __global__ __launch_bounds__(256) void k_window_rows(const int64_t *fptr, const 
         const uint32_t ent = fadj[i];
         const int kr = (int)((int64_t)(ent >> wbits) - w0);          // in (row, nrows)
         atomicOr(&rf[kr >> 5], 1u << (kr & 31));
-        if ((ent & wmask) == 1u) {
-            atomicOr(&r1[kr >> 5], 1u << (kr & 31));
-            atomicOr(&bi1[(int64_t)kr * nwords + (row >> 5)], 1u << (row & 31));
-        }
+        if ((ent & wmask) == 1u) atomicOr(&r1[kr >> 5], 1u << (kr & 31));
     }
     __syncthreads();
     block_popcount_prefix(rf, nwords, pre, wsum);
@@ -1530,6 +1526,35 @@ __global__ __launch_bounds__(256) void k_window_rows(const int64_t *fptr, const 
         bf[ro + w] = rf[w];
         bf1[ro + w] = r1[w];
         pf[ro + w] = (uint32_t)pre[w];
+    }
+}
+
+// bi1, the transpose of bf1 as an nrows x nrows bit matrix: one wave per 64
+// rows and 8 words (256 columns) of bf1; bit j of word J over the 64 rows is
+// one ballot, whose halves are words 2X and 2X + 1 of bi1's row 32 J + j.
+// Every word of bi1 is written once.
+__global__ __launch_bounds__(256) void k_window_transpose(const uint32_t *bf1, int nrows, int nwords, uint32_t *bi1) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nx = (nrows + 63) / 64, nj = (nwords + 7) / 8;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+    for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; t < nx * nj; t += nw) {
+        const int X = (int)(t / nj), J0 = (int)(t % nj) * 8;
+        const int x = X * 64 + lane;
+        uint32_t w[8];
+#pragma unroll
+        for (int jw = 0; jw < 8; jw++)
+            w[jw] = (x < nrows && J0 + jw < nwords) ? bf1[(int64_t)x * nwords + J0 + jw] : 0u;
+#pragma unroll
+        for (int jw = 0; jw < 8; jw++) {
+            uint32_t out = 0u;
+#pragma unroll
+            for (int j = 0; j < 32; j++) {
+                const uint64_t b = __ballot((w[jw] >> j) & 1u);
+                if ((lane & 31) == j) out = lane < 32 ? (uint32_t)b : (uint32_t)(b >> 32);
+            }
+            const int c = 32 * (J0 + jw) + (lane & 31), word = 2 * X + (lane >> 5);
+            if (c < nrows && word < nwords) bi1[(int64_t)c * nwords + word] = out;
+        }
     }
 }
 
@@ -1890,11 +1915,16 @@ void close_window(Graph &g, const WindowPlan &w, uint32_t emask, const uint8_t *
     DBuf<uint32_t> bf(A, cells), bf1(A, cells), bi1(A, cells);
     DBuf<uint32_t> pf(A, cells);
     DBuf<unsigned int> queue(A, 1);
-    fill_u32(bi1.p, cells, 0, s);
     fill_u32(queue.p, 1, 0, s);
     hipLaunchKernelGGL(k_window_rows, dim3(w.nrows), dim3(256), (size_t)3 * w.nwords * sizeof(uint32_t), s, g.fptr.p,
-                       g.fadj.p, g.wbits, w.w0, w.nwords, bf.p, bf1.p, bi1.p, pf.p);
+                       g.fadj.p, g.wbits, w.w0, w.nwords, bf.p, bf1.p, pf.p);
     HTRI_LAUNCH_CHECK();
+    {
+        const int64_t tasks = (int64_t)((w.nrows + 63) / 64) * ((w.nwords + 7) / 8);
+        hipLaunchKernelGGL(k_window_transpose, dim3(grid_for(tasks * kWave, 256, 8192)), dim3(256), 0, s, bf1.p,
+                           w.nrows, w.nwords, bi1.p);
+        HTRI_LAUNCH_CHECK();
+    }
     WinArgs a;
     a.G = graph_desc(g);
     a.w0 = w.w0;
